@@ -1,0 +1,185 @@
+"""FP64 CPU oracle for Cleora propagation -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the CPU-baseline leg of ``bench.py`` may
+import this package.  The GPU library never calls it and shares no code with
+it.  The arithmetic lives in ``cleora_oracle.c`` (plain C, FP64); this module
+compiles it with gcc on first use and marshals numpy arrays.
+
+Functions follow the paper (arXiv 2102.02302):
+  * ``build_adjacency`` -- e_ab counts / weight sums (Section 3.2)
+  * ``transition``      -- M = D^-1 A (Section 3.2, Algorithm 1)
+  * ``init``            -- T_0 ~ U(-1, 1) (Section 3.2)
+  * ``propagate``       -- I iterations of multiply + row L2 normalise
+                           (Algorithm 1)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cleora_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+EMPTY_KEEP = 1
+NO_NORM = 2
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build()
+        lib = ctypes.CDLL(LIB)
+        i64, i32, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+        p = ctypes.c_void_p
+        lib.oracle_splitmix64.restype = u64
+        lib.oracle_splitmix64.argtypes = [u64]
+        lib.oracle_uniform.restype = ctypes.c_double
+        lib.oracle_uniform.argtypes = [u64, i64, i32, i32]
+        lib.oracle_init.restype = None
+        lib.oracle_init.argtypes = [u64, i64, i64, i32, p]
+        lib.oracle_entry_bound.restype = i64
+        lib.oracle_entry_bound.argtypes = [i64, ctypes.c_int]
+        lib.oracle_build_adjacency.restype = ctypes.c_int
+        lib.oracle_build_adjacency.argtypes = [i64, i64, p, p, p, ctypes.c_int, p, p, p,
+                                               ctypes.POINTER(i64)]
+        lib.oracle_transition.restype = None
+        lib.oracle_transition.argtypes = [i64, p, p, p, p]
+        lib.oracle_step_rows.restype = None
+        lib.oracle_step_rows.argtypes = [i64, i64, i32, p, p, p, p, p, ctypes.c_uint]
+        lib.oracle_propagate.restype = None
+        lib.oracle_propagate.argtypes = [i64, i32, p, p, p, p, p, ctypes.c_int, ctypes.c_uint]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_get_threads.restype = ctypes.c_int
+        lib.oracle_get_threads.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(_load().oracle_get_threads())
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().oracle_splitmix64(ctypes.c_uint64(x & (2**64 - 1))))
+
+
+def uniform(seed: int, i: int, d: int, j: int) -> float:
+    return float(_load().oracle_uniform(seed & (2**64 - 1), i, d, j))
+
+
+def init(seed: int, n: int, d: int, row0: int = 0) -> np.ndarray:
+    """T_0 rows row0 .. row0+n-1 (graph-local indices), float64 n x d."""
+    T = np.empty((n, d), np.float64)
+    _load().oracle_init(seed & (2**64 - 1), row0, n, d, _ptr(T))
+    return T
+
+
+class Adjacency:
+    """A in CSR: row_ptr int64[n+1], col int32[nnz], aval float64[nnz]."""
+
+    def __init__(self, n, row_ptr, col, aval):
+        self.n = n
+        self.row_ptr = row_ptr
+        self.col = col
+        self.aval = aval
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def build_adjacency(n: int, src: np.ndarray, dst: np.ndarray, w: Optional[np.ndarray],
+                    directed: bool) -> Adjacency:
+    lib = _load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    if w is not None:
+        w = np.ascontiguousarray(w, np.float32)
+    m = src.size
+    cap = max(1, int(lib.oracle_entry_bound(m, int(directed))))
+    row_ptr = np.empty(n + 1, np.int64)
+    col = np.empty(cap, np.int32)
+    aval = np.empty(cap, np.float64)
+    nnz = ctypes.c_int64(0)
+    rc = lib.oracle_build_adjacency(n, m, _ptr(src), _ptr(dst), _ptr(w), int(directed),
+                                    _ptr(row_ptr), _ptr(col), _ptr(aval), ctypes.byref(nnz))
+    if rc == -1:
+        raise ValueError("edge id outside [0, n) or weight not finite and positive")
+    if rc != 0:
+        raise MemoryError("oracle adjacency build ran out of memory")
+    k = nnz.value
+    return Adjacency(n, row_ptr, col[:k].copy(), aval[:k].copy())
+
+
+def build_graph(g) -> Adjacency:
+    """Adjacency of a ``gen.Graph``."""
+    return build_adjacency(g.n, g.src, g.dst, g.w, g.directed)
+
+
+def transition(adj: Adjacency) -> tuple[np.ndarray, np.ndarray]:
+    """(mval float64[nnz], deg float64[n]) with mval = aval / deg[row]."""
+    mval = np.empty(max(1, adj.nnz), np.float64)
+    deg = np.empty(adj.n, np.float64)
+    _load().oracle_transition(adj.n, _ptr(adj.row_ptr), _ptr(adj.aval), _ptr(mval), _ptr(deg))
+    return mval[:adj.nnz], deg
+
+
+def step_rows(adj: Adjacency, mval: np.ndarray, T_in: np.ndarray, T_out: np.ndarray,
+              r0: int, r1: int, flags: int = 0) -> None:
+    """One iteration for rows [r0, r1) into T_out (other rows untouched)."""
+    assert T_in.dtype == np.float64 and T_in.flags.c_contiguous
+    assert T_out.dtype == np.float64 and T_out.flags.c_contiguous
+    d = T_in.shape[1]
+    _load().oracle_step_rows(r0, r1, d, _ptr(adj.row_ptr), _ptr(adj.col), _ptr(mval),
+                             _ptr(T_in), _ptr(T_out), flags)
+
+
+def propagate(adj: Adjacency, mval: np.ndarray, T0: np.ndarray, k: int,
+              flags: int = 0) -> np.ndarray:
+    """T_k from T_0 (float64 n x d); returns a new array."""
+    T = np.array(T0, dtype=np.float64, order="C", copy=True)
+    tmp = np.empty_like(T)
+    n, d = T.shape
+    assert n == adj.n
+    _load().oracle_propagate(n, d, _ptr(adj.row_ptr), _ptr(adj.col), _ptr(mval), _ptr(T),
+                             _ptr(tmp), int(k), flags)
+    return T
+
+
+def embed(g, d: int, k: int, seed: int, flags: int = 0) -> np.ndarray:
+    """Whole path for one graph: A -> M -> T_0(seed) -> T_k."""
+    adj = build_graph(g)
+    mval, _ = transition(adj)
+    T0 = init(seed, g.n, d)
+    return propagate(adj, mval, T0, k, flags)
