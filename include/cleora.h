@@ -1,0 +1,186 @@
+/*
+ * cleora.h -- C ABI of the MI355X (gfx950) Cleora propagation library.
+ *
+ * The method (Rychalska et al., "Cleora: A Simple, Strong and Scalable Graph
+ * Embedding Scheme", arXiv 2102.02302, Section 3.2 and Algorithm 1):
+ *   M = D^-1 A, the random-walk transition matrix of a graph, with
+ *       A[a][b] = e_ab (number of a->b edges, or the sum of their weights)
+ *       and D[a] = sum_b A[a][b];
+ *   T_0 ~ U(-1, 1), an N x d matrix;
+ *   repeat I times: T_i = M . T_{i-1}, then L2-normalise every row of T_i.
+ *
+ * Conventions for every call below:
+ *   - All functions return CLEORA_OK (0) or one of the CLEORA_E_* codes and
+ *     never throw; cleora_last_error() gives a message for the calling thread.
+ *   - "device pointer" means memory the GPU of the context can read or write
+ *     (hipMalloc / torch CUDA tensors).  "stream" is a hipStream_t passed as
+ *     void*; NULL means the default stream.  Work is queued on that stream;
+ *     calls return before it finishes unless stated otherwise.
+ *   - Input buffers must stay alive and unchanged until the stream has
+ *     passed the call.  Everything the library allocates belongs to the
+ *     context and is released by cleora_destroy.
+ *   - A context is not thread-safe.  Separate contexts are independent.
+ */
+#ifndef CLEORA_H
+#define CLEORA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define CLEORA_OK 0
+#define CLEORA_E_INVAL 1  /* bad argument (null pointer, size out of range) */
+#define CLEORA_E_STATE 2  /* call out of order (no graph, no embedding)    */
+#define CLEORA_E_NOMEM 3  /* device allocation failed                      */
+#define CLEORA_E_DEVICE 4 /* HIP runtime error                             */
+#define CLEORA_E_INPUT 5  /* edge id outside [0, n) or weight not finite>0  */
+
+/* ---------------------------------------------------------- data types */
+#define CLEORA_F32 0  /* embeddings stored as float32                     */
+#define CLEORA_BF16 1 /* stored as bfloat16 (round to nearest even);
+                         products, sums and row norms are float32         */
+
+/* ---------------------------------------------------------------- flags */
+#define CLEORA_DIRECTED 1u   /* edge (a,b) counts only for a->b; default:
+                                undirected, stored as a->b and b->a, a loop
+                                {a,a} once (Section 3.2, Section 4.5)       */
+#define CLEORA_EMPTY_KEEP 2u /* a node with no out-edges keeps its previous
+                                row (normalised); default: its row becomes
+                                zero, since row a of M is zero              */
+
+/* Largest embedding dimension supported: 4096 (float32) / 8192 (bf16). */
+#define CLEORA_MAX_DIM_F32 4096
+#define CLEORA_MAX_DIM_BF16 8192
+
+typedef struct cleora_ctx cleora_ctx;
+
+/* Create a context on HIP device `device`.  *out receives the handle.
+ * Errors: E_INVAL (out NULL), E_DEVICE (no such device). */
+int cleora_create(cleora_ctx **out, int device);
+
+/* Release the context and all device memory it owns.  Waits for work the
+ * context queued.  NULL is ignored. */
+void cleora_destroy(cleora_ctx *ctx);
+
+/* Device bytes a context needs to embed a graph with n_nodes nodes and
+ * n_edges input edges at the given dim and dtype (the memory model of
+ * Section 4.5 -- one sparse matrix plus two N x d embedding buffers -- plus
+ * the build and hub-row scratch of this implementation).  An upper bound,
+ * used for admission decisions.  Returns 0 for invalid arguments. */
+size_t cleora_footprint_bytes(int64_t n_nodes, int64_t n_edges, uint32_t flags, int32_t dim,
+                              int32_t dtype);
+
+/* Build M = D^-1 A (Section 3.2) on the GPU from an edge list.
+ *   n_nodes  number of nodes N, 1 <= N < 2^31
+ *   n_edges  number of edges m >= 0 (m = 0 gives an empty graph)
+ *   src,dst  device int32[m]: edge a->b is (src[e], dst[e]); ids in [0, N)
+ *   w        device float32[m] weights (finite, > 0), or NULL: every edge
+ *            counts 1
+ *   flags    CLEORA_DIRECTED and/or CLEORA_EMPTY_KEEP
+ * Result (owned by ctx): CSR with rows ascending, columns ascending within
+ * a row, repeated pairs merged by summing (e_ab), D[a] summed in float64,
+ * M values rounded to float32.  Replaces any previous graph and embedding.
+ * Synchronises the stream once at the end (to size the result).
+ * Errors: E_INVAL (sizes, null pointers), E_INPUT (an id out of range or a
+ * bad weight; the context then holds no graph), E_NOMEM, E_DEVICE. */
+int cleora_build_csr(cleora_ctx *ctx, int64_t n_nodes, int64_t n_edges, const int32_t *src,
+                     const int32_t *dst, const float *w, uint32_t flags, void *stream);
+
+/* Initialise T_0 (Section 3.2: T_0 ~ U(-1, 1)) for the current graph:
+ *   T_0[i][j] = k / 2^23 - 1,  k = splitmix64(seed ^ splitmix64(i*dim + j)) >> 40
+ * (SplitMix64 output function of Steele, Lea and Flood, 2014), exact in
+ * float32, rounded to nearest even for CLEORA_BF16.  Also plans the
+ * propagation schedule for this dim and synchronises the stream once.
+ * Resets the iteration count to 0.
+ * Errors: E_STATE (no graph), E_INVAL (dim < 1 or above the maximum, bad
+ * dtype), E_NOMEM, E_DEVICE. */
+int cleora_init(cleora_ctx *ctx, int32_t dim, int32_t dtype, uint64_t seed, void *stream);
+
+/* Run k more iterations of Algorithm 1 (multiply by M, then L2-normalise
+ * each row; a row whose product is exactly zero becomes zero, see
+ * CLEORA_EMPTY_KEEP).  k = 0 does nothing.  Calls continue from the current
+ * iteration: propagate(a) then propagate(b) equals propagate(a + b) bit for
+ * bit.  Errors: E_INVAL (k < 0), E_STATE (no embedding), E_DEVICE. */
+int cleora_propagate(cleora_ctx *ctx, int32_t k, void *stream);
+
+/* Copy the current N x dim embedding into dst (device or host memory; a
+ * host destination should be pinned) with a row stride of ld elements
+ * (ld >= dim).  dst_dtype must equal the context dtype, or be CLEORA_F32
+ * for a CLEORA_BF16 context (widened on the GPU; device dst only).
+ * Errors: E_STATE, E_INVAL, E_DEVICE. */
+int cleora_get_embedding(cleora_ctx *ctx, void *dst, int64_t ld, int32_t dst_dtype, void *stream);
+
+/* Device pointer and row stride (elements) of the current embedding
+ * buffer; valid until the next propagate, init, build or destroy. */
+int cleora_embedding_ptr(cleora_ctx *ctx, const void **ptr, int64_t *ld);
+
+/* Copy the built CSR into caller device buffers: row_ptr int64[N+1],
+ * col int32[nnz], val float32[nnz] (M values), deg float64[N] (D).  Any of
+ * them may be NULL.  Sizes come from cleora_info.  Errors: E_STATE. */
+int cleora_get_csr(cleora_ctx *ctx, int64_t *row_ptr, int32_t *col, float *val, double *deg,
+                   void *stream);
+
+/* Sizes and state: any pointer may be NULL. */
+int cleora_info(cleora_ctx *ctx, int64_t *n_nodes, int64_t *nnz, int32_t *dim, int32_t *dtype,
+                int32_t *iteration);
+
+/* Wait for the stream.  Errors: E_DEVICE. */
+int cleora_sync(cleora_ctx *ctx, void *stream);
+
+/* Per-context tuning: nnz per work item for the SpMM (the unit of load
+ * balance; rows longer than this are split and their partial sums combined
+ * in a fixed order).  0 restores the default.  Takes effect at the next
+ * cleora_init.  Errors: E_INVAL (chunk < 0 or > 2^20). */
+int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
+
+/* Kernel timing for measurement: when on, the library records HIP events
+ * around every SpMM+normalise launch on the launch stream and accumulates
+ * their durations; cleora_kernel_time returns the total milliseconds and
+ * the number of launches timed since the last reset (and resets). */
+int cleora_set_timing(cleora_ctx *ctx, int on);
+int cleora_kernel_time(cleora_ctx *ctx, double *spmm_ms, int64_t *spmm_launches,
+                       double *combine_ms, int64_t *combine_launches);
+
+/* ------------------------------------------------------ batched form */
+
+/* One graph of a batch.  Pointers are device pointers as in
+ * cleora_build_csr; seed keys that graph's T_0 by its own node indices, so
+ * a graph embeds to the same bits alone or in any batch. */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_edges;
+    const int32_t *src;
+    const int32_t *dst;
+    const float *w; /* NULL: unweighted */
+    uint64_t seed;
+} cleora_graph;
+
+/* Embed n_graphs independent graphs as one block-diagonal graph: one CSR
+ * build, one T_0 initialisation and k iterations over all of them at once.
+ * out[g] is a device float32/bf16 (per dtype) buffer of graphs[g].n_nodes x
+ * dim elements, row stride dim.  The context's graph and embedding are
+ * replaced by the block-diagonal ones.  Errors: as build/init/propagate;
+ * any failure writes no output. */
+int cleora_embed_batch(cleora_ctx *ctx, int32_t n_graphs, const cleora_graph *graphs,
+                       uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
+                       void *stream);
+
+/* Continuous batching: advance each of n contexts (each with an embedding,
+ * all with the same dim and dtype) by ONE iteration, every context's rows
+ * in the same kernel launches.  Each context's result is bit-identical to
+ * cleora_propagate(ctx, 1).  Errors: E_INVAL (mixed dim/dtype, n < 0),
+ * E_STATE, E_DEVICE. */
+int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream);
+
+/* Message for the last error on this thread ("" if none). */
+const char *cleora_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLEORA_H */

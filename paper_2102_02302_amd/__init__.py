@@ -1,0 +1,221 @@
+"""MI355X (gfx950) implementation of Cleora's propagation hot path.
+
+Cleora (Rychalska et al., arXiv 2102.02302, Section 3.2, Algorithm 1) embeds
+a graph by repeating T_i = normalise_rows(M . T_{i-1}) with M = D^-1 A and
+T_0 ~ U(-1, 1).  The work runs in the HIP library ``libcleora.so`` behind the
+C ABI of ``include/cleora.h``; this package only marshals torch tensors
+(device memory) and streams into those calls.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+from . import _lib
+from ._lib import BF16, DIRECTED, EMPTY_KEEP, F32, CleoraError, load  # noqa: F401
+
+__all__ = ["Context", "embed", "embed_batch", "step_multi", "footprint_bytes", "CleoraError",
+           "F32", "BF16", "DIRECTED", "EMPTY_KEEP", "load"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in (F32, "f32", "float32", "fp32"):
+        return F32
+    if dtype in (BF16, "bf16", "bfloat16"):
+        return BF16
+    torch = _torch()
+    if dtype is torch.float32:
+        return F32
+    if dtype is torch.bfloat16:
+        return BF16
+    raise ValueError(f"unknown dtype {dtype!r}")
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(x, device):
+    torch = _torch()
+    t = torch.as_tensor(x)
+    return t.to(device=device, dtype=torch.int32).contiguous()
+
+
+def _dev_f32(x, device):
+    if x is None:
+        return None
+    torch = _torch()
+    return torch.as_tensor(x).to(device=device, dtype=torch.float32).contiguous()
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def footprint_bytes(n_nodes: int, n_edges: int, dim: int, dtype="f32",
+                    directed: bool = False) -> int:
+    return int(load().cleora_footprint_bytes(n_nodes, n_edges, DIRECTED if directed else 0, dim,
+                                             _dtype_code(dtype)))
+
+
+class Context:
+    """One graph and its embedding on one GPU (a ``cleora_ctx``)."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        self._lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _lib.check(self._lib.cleora_create(ctypes.byref(h), device))
+        self._h = h
+        self._keep = []  # inputs that must outlive queued work
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.cleora_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    # -- calls
+    def build_csr(self, n_nodes: int, src, dst, w=None, directed: bool = False,
+                  empty_keep: bool = False, stream=None) -> "Context":
+        s = _dev_i32(src, self.device)
+        d = _dev_i32(dst, self.device)
+        wt = _dev_f32(w, self.device)
+        flags = (DIRECTED if directed else 0) | (EMPTY_KEEP if empty_keep else 0)
+        _lib.check(self._lib.cleora_build_csr(self._h, int(n_nodes), int(s.numel()), _ptr(s),
+                                              _ptr(d), _ptr(wt), flags, _stream(stream)))
+        self._keep = [s, d, wt]
+        return self
+
+    def build_graph(self, g, empty_keep: bool = False, stream=None) -> "Context":
+        """Build from a ``gen.Graph``-like object (n, src, dst, w, directed)."""
+        return self.build_csr(g.n, g.src, g.dst, g.w, g.directed, empty_keep, stream)
+
+    def set_chunk(self, chunk: int) -> None:
+        _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
+
+    def init(self, dim: int, dtype="f32", seed: int = 0, stream=None) -> "Context":
+        _lib.check(self._lib.cleora_init(self._h, int(dim), _dtype_code(dtype),
+                                         int(seed) & (2**64 - 1), _stream(stream)))
+        return self
+
+    def propagate(self, k: int, stream=None) -> "Context":
+        _lib.check(self._lib.cleora_propagate(self._h, int(k), _stream(stream)))
+        return self
+
+    def sync(self, stream=None) -> None:
+        _lib.check(self._lib.cleora_sync(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        n, nnz = ctypes.c_int64(), ctypes.c_int64()
+        dim, dt, it = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self._lib.cleora_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
+                                         ctypes.byref(dim), ctypes.byref(dt), ctypes.byref(it)))
+        return {"n": n.value, "nnz": nnz.value, "dim": dim.value, "dtype": dt.value,
+                "iteration": it.value}
+
+    def embedding(self, dtype=None, stream=None):
+        """Copy of the current N x dim embedding as a device tensor."""
+        torch = _torch()
+        inf = self.info()
+        code = inf["dtype"] if dtype is None else _dtype_code(dtype)
+        tdt = torch.float32 if code == F32 else torch.bfloat16
+        out = torch.empty((inf["n"], inf["dim"]), dtype=tdt, device=self.device)
+        _lib.check(self._lib.cleora_get_embedding(self._h, out.data_ptr(), inf["dim"], code,
+                                                  _stream(stream)))
+        return out
+
+    def csr(self, stream=None) -> dict:
+        torch = _torch()
+        inf = self.info()
+        n, nnz = inf["n"], inf["nnz"]
+        rp = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(nnz, 1), dtype=torch.float32, device=self.device)
+        deg = torch.empty(n, dtype=torch.float64, device=self.device)
+        _lib.check(self._lib.cleora_get_csr(self._h, rp.data_ptr(), col.data_ptr(),
+                                            val.data_ptr(), deg.data_ptr(), _stream(stream)))
+        return {"row_ptr": rp, "col": col[:nnz], "val": val[:nnz], "deg": deg}
+
+    # -- measurement
+    def set_timing(self, on: bool) -> None:
+        _lib.check(self._lib.cleora_set_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self) -> dict:
+        a, b = ctypes.c_double(), ctypes.c_double()
+        na, nb = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.cleora_kernel_time(self._h, ctypes.byref(a), ctypes.byref(na),
+                                                ctypes.byref(b), ctypes.byref(nb)))
+        return {"spmm_ms": a.value, "spmm_launches": na.value, "combine_ms": b.value,
+                "combine_launches": nb.value}
+
+
+def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
+          empty_keep: bool = False, chunk: int = 0):
+    """Whole path for one graph: build M, initialise T_0, k iterations."""
+    with Context(device) as ctx:
+        ctx.build_graph(g, empty_keep=empty_keep)
+        if chunk:
+            ctx.set_chunk(chunk)
+        ctx.init(dim, dtype, seed)
+        ctx.propagate(k)
+        return ctx.embedding()
+
+
+def embed_batch(ctx: Context, graphs: Sequence, dim: int, k: int, seeds: Sequence[int],
+                dtype="f32", directed: bool = False, empty_keep: bool = False,
+                stream=None) -> List:
+    """Embed several graphs as one block-diagonal graph (cleora_embed_batch)."""
+    torch = _torch()
+    code = _dtype_code(dtype)
+    tdt = torch.float32 if code == F32 else torch.bfloat16
+    arr = (_lib.Graph * len(graphs))()
+    keep, outs = [], []
+    for i, g in enumerate(graphs):
+        s = _dev_i32(g.src, ctx.device)
+        d = _dev_i32(g.dst, ctx.device)
+        w = _dev_f32(g.w, ctx.device)
+        keep += [s, d, w]
+        arr[i] = _lib.Graph(g.n, s.numel(), _ptr(s), _ptr(d), _ptr(w),
+                            int(seeds[i]) & (2**64 - 1))
+        outs.append(torch.empty((g.n, dim), dtype=tdt, device=ctx.device))
+    out_ptrs = (ctypes.c_void_p * len(graphs))(*[o.data_ptr() for o in outs])
+    flags = (DIRECTED if directed else 0) | (EMPTY_KEEP if empty_keep else 0)
+    _lib.check(ctx._lib.cleora_embed_batch(ctx.handle, len(graphs), arr, flags, dim, code, k,
+                                           out_ptrs, _stream(stream)))
+    return outs
+
+
+def step_multi(ctxs: Sequence[Context], stream=None) -> None:
+    """One iteration for every context in a single set of launches."""
+    if not ctxs:
+        return
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.handle.value for c in ctxs])
+    _lib.check(ctxs[0]._lib.cleora_step_multi(arr, len(ctxs), _stream(stream)))

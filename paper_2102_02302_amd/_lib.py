@@ -1,0 +1,93 @@
+"""ctypes binding of libcleora.so (the C ABI in include/cleora.h).
+
+Argument marshalling only: every step of the embedding runs in the HIP
+library.  Loading fails loudly when the library has not been built; there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("CLEORA_LIB", os.path.join(_HERE, "libcleora.so"))
+
+OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_INPUT = range(6)
+F32, BF16 = 0, 1
+DIRECTED, EMPTY_KEEP = 1, 2
+MAX_DIM = {F32: 4096, BF16: 8192}
+
+_CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
+          E_DEVICE: "E_DEVICE", E_INPUT: "E_INPUT"}
+
+EXPORTS = [
+    "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
+    "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
+    "cleora_get_csr", "cleora_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
+    "cleora_kernel_time", "cleora_embed_batch", "cleora_step_multi", "cleora_last_error",
+]
+
+
+class CleoraError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2102_02302_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                             ctypes.c_uint64)
+    sig = {
+        "cleora_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.c_int]),
+        "cleora_destroy": (None, [p]),
+        "cleora_footprint_bytes": (ctypes.c_size_t, [i64, i64, u32, i32, i32]),
+        "cleora_build_csr": (ctypes.c_int, [p, i64, i64, p, p, p, u32, p]),
+        "cleora_init": (ctypes.c_int, [p, i32, i32, u64, p]),
+        "cleora_propagate": (ctypes.c_int, [p, i32, p]),
+        "cleora_get_embedding": (ctypes.c_int, [p, p, i64, i32, p]),
+        "cleora_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p), ctypes.POINTER(i64)]),
+        "cleora_get_csr": (ctypes.c_int, [p, p, p, p, p, p]),
+        "cleora_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                       ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]),
+        "cleora_sync": (ctypes.c_int, [p, p]),
+        "cleora_set_chunk": (ctypes.c_int, [p, i32]),
+        "cleora_set_timing": (ctypes.c_int, [p, ctypes.c_int]),
+        "cleora_kernel_time": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(i64),
+                                              ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(i64)]),
+        "cleora_embed_batch": (ctypes.c_int, [p, i32, ctypes.POINTER(Graph), u32, i32, i32, i32,
+                                              ctypes.POINTER(p), p]),
+        "cleora_step_multi": (ctypes.c_int, [ctypes.POINTER(p), i32, p]),
+        "cleora_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        msg = load().cleora_last_error()
+        raise CleoraError(rc, msg.decode() if msg else "")

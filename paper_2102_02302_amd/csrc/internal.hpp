@@ -1,0 +1,113 @@
+// Internal declarations shared by the translation units of the library.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace cleora {
+
+// ------------------------------------------------------------------ scan
+
+// Workspace (int64 elements) that exclusive_scan needs for n inputs.
+size_t scan_workspace_elems(int64_t n);
+// out[i] = sum of in[0..i), i = 0..n (out has n+1 entries; out[n] = total).
+void exclusive_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *ws, hipStream_t s);
+void exclusive_scan(const uint8_t *in, int64_t n, int64_t *out, int64_t *ws, hipStream_t s);
+void exclusive_scan(const int64_t *in, int64_t n, int64_t *out, int64_t *ws, hipStream_t s);
+
+// ----------------------------------------------------- propagation step
+
+// Everything one context contributes to a propagation launch.  Stored in
+// device memory; a launch covers one or more contexts, each owning the
+// waves [wave_begin, wave_begin + n_split + n_buckets) of the SpMM launch
+// and the blocks [block_begin, block_begin + n_long) of the combine launch.
+struct StepDesc {
+    const int64_t *rp;        // CSR row pointers, N+1
+    const int32_t *col;       // CSR columns
+    const float *val;         // M values
+    const void *Ein;          // T_{t-1}, N x ld
+    void *Eout;               // T_t,     N x ld
+    float *partial;           // n_split x ld float32 partial sums of split rows
+    const int2 *split_items;  // (row, chunk index) of every split chunk
+    const int32_t *bucket_row;  // n_buckets+1 row boundaries of the packed items
+    const int32_t *long_rows;   // rows split into chunks, ascending
+    const int64_t *chunk_base;  // N+1: first partial slot of each row
+    int64_t wave_begin;
+    int64_t block_begin;
+    int64_t n_split;
+    int64_t n_buckets;
+    int64_t n_long;
+    int32_t ld;
+    int32_t chunk;
+    uint32_t flags;
+    int32_t pad_;
+};
+
+// Kernel variant for an embedding layout.
+struct Variant {
+    int dtype;  // CLEORA_F32 / CLEORA_BF16
+    int cpr;    // 16-byte vectors per embedding row
+    int G;      // rows of T gathered at once per wave (groups of 64/G lanes)
+    int VPL;    // 16-byte vectors per lane
+    int cprf;   // float4 vectors per partial (float32) row
+    int VPLF;   // float4 vectors per lane in the combine kernel
+};
+Variant choose_variant(int dtype, int ld);
+
+void launch_spmm(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
+                 hipStream_t s);
+void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,
+                    hipStream_t s);
+// T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and
+// local indices), or a single graph when n_graphs == 1 and row0 == nullptr.
+void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
+                 const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s);
+void launch_widen_bf16(const void *src, int64_t n, int32_t dim, int32_t ld_src, float *dst,
+                       int64_t ld_dst, hipStream_t s);
+
+}  // namespace cleora
+
+// ------------------------------------------------------------------- ctx
+
+struct cleora_ctx {
+    int device = 0;
+
+    // graph (CSR of M)
+    bool has_graph = false;
+    int64_t n = 0, nnz = 0, m_in = 0;
+    uint32_t flags = 0;
+    cleora::DevBuf rp, col, val, deg;
+
+    // embedding
+    bool has_emb = false;
+    int32_t dim = 0, dtype = 0, ld = 0, iteration = 0, cur = 0;
+    cleora::DevBuf E[2];
+
+    // schedule
+    int32_t chunk_req = 0, chunk = 0;
+    int64_t n_split = 0, n_buckets = 0, n_long = 0;
+    cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
+
+    // build temporaries (grow-only)
+    cleora::DevBuf t_edges, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
+        t_scan, t_small, multi_desc;
+    int64_t *h_small = nullptr;  // pinned host mirror of t_small
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmm, ev_comb;
+    size_t ev_next = 0;
+};
+
+namespace cleora {
+// CSR build from edges already in device memory (build_csr.hip).
+void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                 const float *w, uint32_t flags, hipStream_t s);
+// Propagation schedule for the current graph and chunk (propagate.hip).
+void plan_schedule(cleora_ctx *c, hipStream_t s);
+// Fill the two per-parity step descriptors of a context.
+void write_descs(cleora_ctx *c, hipStream_t s);
+StepDesc host_desc(const cleora_ctx *c, int parity);
+}  // namespace cleora

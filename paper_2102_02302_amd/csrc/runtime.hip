@@ -1,0 +1,498 @@
+// C ABI of the library: contexts, argument checks, launches, errors.
+// Every entry point catches everything and returns a CLEORA_* status.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using cleora::DevBuf;
+using cleora::Error;
+using cleora::StepDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define ABI_BEGIN try {
+#define ABI_END                                                                 \
+    }                                                                           \
+    catch (const Error &e) { return fail(e.code, e.what()); }                   \
+    catch (const std::bad_alloc &) { return fail(CLEORA_E_NOMEM, "host allocation failed"); } \
+    catch (const std::exception &e) { return fail(CLEORA_E_DEVICE, e.what()); } \
+    catch (...) { return fail(CLEORA_E_DEVICE, "unknown error"); }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) CLEORA_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int elem_size(int dtype) { return dtype == CLEORA_BF16 ? 2 : 4; }
+
+int32_t padded_ld(int32_t dim, int dtype)
+{
+    const int epv = 16 / elem_size(dtype);
+    return (dim + epv - 1) / epv * epv;
+}
+
+// Entries per work item: about 512 KiB of gathered rows per item, within
+// [64, 2048] entries.
+int32_t default_chunk(int32_t ld, int dtype)
+{
+    const int64_t row_bytes = (int64_t)ld * elem_size(dtype);
+    const int64_t c = (512 * 1024) / std::max<int64_t>(row_bytes, 1);
+    return (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, c));
+}
+
+void check_dim(int32_t dim, int32_t dtype)
+{
+    if (dtype != CLEORA_F32 && dtype != CLEORA_BF16) throw Error(CLEORA_E_INVAL, "unknown dtype");
+    const int32_t mx = dtype == CLEORA_BF16 ? CLEORA_MAX_DIM_BF16 : CLEORA_MAX_DIM_F32;
+    if (dim < 1 || dim > mx)
+        throw Error(CLEORA_E_INVAL, "dim must be in [1, " + std::to_string(mx) + "]");
+}
+
+void check_graph_sizes(int64_t n, int64_t m)
+{
+    if (n < 1 || n > 0x7fffffffLL) throw Error(CLEORA_E_INVAL, "n_nodes must be in [1, 2^31-1]");
+    if (m < 0 || m > ((int64_t)1 << 40)) throw Error(CLEORA_E_INVAL, "n_edges out of range");
+}
+
+hipEvent_t take_event(cleora_ctx *c)
+{
+    if (c->ev_next < c->ev_pool.size()) return c->ev_pool[c->ev_next++];
+    hipEvent_t e;
+    CLEORA_HIP(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+    c->ev_next = c->ev_pool.size();
+    return e;
+}
+
+void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
+{
+    const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
+    for (int32_t t = 0; t < k; ++t) {
+        const StepDesc *d = c->desc.as<StepDesc>() + c->cur;
+        hipEvent_t a = nullptr, b = nullptr;
+        if (c->timing) {
+            a = take_event(c);
+            b = take_event(c);
+            CLEORA_HIP(hipEventRecord(a, s));
+        }
+        cleora::launch_spmm(v, d, 1, c->n_split + c->n_buckets, s);
+        if (c->timing) {
+            CLEORA_HIP(hipEventRecord(b, s));
+            c->ev_spmm.emplace_back(a, b);
+        }
+        if (c->n_long > 0) {
+            if (c->timing) {
+                a = take_event(c);
+                b = take_event(c);
+                CLEORA_HIP(hipEventRecord(a, s));
+            }
+            cleora::launch_combine(v, d, 1, c->n_long, s);
+            if (c->timing) {
+                CLEORA_HIP(hipEventRecord(b, s));
+                c->ev_comb.emplace_back(a, b);
+            }
+        }
+        c->cur ^= 1;
+        c->iteration++;
+    }
+}
+
+void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
+{
+    c->has_emb = false;
+    c->dim = dim;
+    c->dtype = dtype;
+    c->ld = padded_ld(dim, dtype);
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_chunk(c->ld, dtype);
+    const size_t ebytes = (size_t)c->n * (size_t)c->ld * elem_size(dtype);
+    c->E[0].ensure(ebytes);
+    c->E[1].ensure(ebytes);
+    cleora::plan_schedule(c, s);
+    c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
+    cleora::write_descs(c, s);
+    c->cur = 0;
+    c->iteration = 0;
+}
+
+__global__ void k_offset_edges(int64_t m, const int32_t *__restrict__ src,
+                               const int32_t *__restrict__ dst, const float *__restrict__ w,
+                               int64_t n_g, int64_t node_off, int32_t *__restrict__ osrc,
+                               int32_t *__restrict__ odst, float *__restrict__ ow)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = src[e], b = dst[e];
+        // an id outside its own graph stays invalid in the concatenation
+        osrc[e] = (a >= 0 && a < n_g) ? (int32_t)(a + node_off) : -1;
+        odst[e] = (b >= 0 && b < n_g) ? (int32_t)(b + node_off) : -1;
+        if (ow) ow[e] = w ? w[e] : 1.0f;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cleora_last_error(void) { return g_last_error.c_str(); }
+
+int cleora_create(cleora_ctx **out, int device)
+{
+    ABI_BEGIN
+    if (!out) return fail(CLEORA_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    CLEORA_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(CLEORA_E_DEVICE, "no such device");
+    DeviceGuard g(device);
+    cleora_ctx *c = new cleora_ctx();
+    c->device = device;
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_small), 8 * sizeof(int64_t),
+                      hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return fail(CLEORA_E_NOMEM, "pinned host allocation failed");
+    }
+    try {
+        c->t_small.ensure(8 * sizeof(int64_t));
+    } catch (...) {
+        (void)hipHostFree(c->h_small);
+        delete c;
+        throw;
+    }
+    *out = c;
+    return CLEORA_OK;
+    ABI_END
+}
+
+void cleora_destroy(cleora_ctx *c)
+{
+    if (!c) return;
+    try {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        DevBuf *bufs[] = {&c->rp, &c->col, &c->val, &c->deg, &c->E[0], &c->E[1],
+                          &c->split_items, &c->bucket_row, &c->long_rows, &c->chunk_base,
+                          &c->partial, &c->desc, &c->t_edges, &c->t_cnt, &c->t_off, &c->t_keys,
+                          &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
+                          &c->t_scan, &c->t_small, &c->multi_desc};
+        for (DevBuf *b : bufs) b->release();
+        for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+        if (c->h_small) (void)hipHostFree(c->h_small);
+    } catch (...) {
+    }
+    delete c;
+}
+
+size_t cleora_footprint_bytes(int64_t n, int64_t m, uint32_t flags, int32_t dim, int32_t dtype)
+{
+    if (n < 1 || m < 0 || dim < 1 || (dtype != CLEORA_F32 && dtype != CLEORA_BF16)) return 0;
+    const double t = (flags & CLEORA_DIRECTED) ? (double)m : 2.0 * (double)m;
+    const int32_t ld = padded_ld(dim, dtype);
+    const int32_t C = default_chunk(ld, dtype);
+    const double N = (double)n;
+    double b = 0;
+    b += 8 * N + 8 * (N + 1) + 8 * t + 8 * t + t + 8 * (t + 1) + 8 * t + 8 * N;  // build
+    b += 8 * 16.0 * ceil(std::max(t, N) / 4096.0);                             // scan
+    b += 8 * (N + 1) + 4 * t + 4 * t + 8 * N;                                  // CSR + D
+    b += 2.0 * N * ld * elem_size(dtype);                                      // T ping-pong
+    const double split = 2.0 * t / C + 1;
+    b += 8 * (N + 1) + split * (4.0 * ld + 8) + 4 * ((t + N) / C + 2) + 4 * N;  // schedule
+    b += 1 << 20;                                                               // slack
+    return (size_t)b;
+}
+
+int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                     const float *w, uint32_t flags, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    check_graph_sizes(n, m);
+    if (m > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst is NULL");
+    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
+    DeviceGuard g(c->device);
+    cleora::build_graph(c, n, m, src, dst, w, flags, cleora::as_stream(stream));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_init(cleora_ctx *c, int32_t dim, int32_t dtype, uint64_t seed, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (!c->has_graph) return fail(CLEORA_E_STATE, "no graph: call cleora_build_csr first");
+    check_dim(dim, dtype);
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    setup_embedding(c, dim, dtype, s);
+    cleora::launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s);
+    c->has_emb = true;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_propagate(cleora_ctx *c, int32_t k, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
+    if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding: call cleora_init first");
+    DeviceGuard g(c->device);
+    run_steps(c, k, cleora::as_stream(stream));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_get_embedding(cleora_ctx *c, void *dst, int64_t ld, int32_t dst_dtype, void *stream)
+{
+    ABI_BEGIN
+    if (!c || !dst) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
+    if (ld < c->dim) return fail(CLEORA_E_INVAL, "ld < dim");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    if (dst_dtype == c->dtype) {
+        const size_t es = elem_size(c->dtype);
+        CLEORA_HIP(hipMemcpy2DAsync(dst, (size_t)ld * es, c->E[c->cur].p, (size_t)c->ld * es,
+                                    (size_t)c->dim * es, (size_t)c->n, hipMemcpyDefault, s));
+    } else if (c->dtype == CLEORA_BF16 && dst_dtype == CLEORA_F32) {
+        cleora::launch_widen_bf16(c->E[c->cur].p, c->n, c->dim, c->ld,
+                                  reinterpret_cast<float *>(dst), ld, s);
+    } else {
+        return fail(CLEORA_E_INVAL, "unsupported dst_dtype for this context");
+    }
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_embedding_ptr(cleora_ctx *c, const void **ptr, int64_t *ld)
+{
+    ABI_BEGIN
+    if (!c || !ptr) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
+    *ptr = c->E[c->cur].p;
+    if (ld) *ld = c->ld;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_get_csr(cleora_ctx *c, int64_t *row_ptr, int32_t *col, float *val, double *deg,
+                   void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (!c->has_graph) return fail(CLEORA_E_STATE, "no graph");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    if (row_ptr)
+        CLEORA_HIP(hipMemcpyAsync(row_ptr, c->rp.p, sizeof(int64_t) * (c->n + 1), hipMemcpyDefault, s));
+    if (col && c->nnz)
+        CLEORA_HIP(hipMemcpyAsync(col, c->col.p, sizeof(int32_t) * c->nnz, hipMemcpyDefault, s));
+    if (val && c->nnz)
+        CLEORA_HIP(hipMemcpyAsync(val, c->val.p, sizeof(float) * c->nnz, hipMemcpyDefault, s));
+    if (deg) CLEORA_HIP(hipMemcpyAsync(deg, c->deg.p, sizeof(double) * c->n, hipMemcpyDefault, s));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_info(cleora_ctx *c, int64_t *n, int64_t *nnz, int32_t *dim, int32_t *dtype,
+                int32_t *iteration)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (n) *n = c->has_graph ? c->n : 0;
+    if (nnz) *nnz = c->has_graph ? c->nnz : 0;
+    if (dim) *dim = c->has_emb ? c->dim : 0;
+    if (dtype) *dtype = c->dtype;
+    if (iteration) *iteration = c->has_emb ? c->iteration : 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_sync(cleora_ctx *c, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    CLEORA_HIP(hipStreamSynchronize(cleora::as_stream(stream)));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_set_chunk(cleora_ctx *c, int32_t chunk)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (chunk < 0 || chunk > (1 << 20)) return fail(CLEORA_E_INVAL, "chunk out of range");
+    c->chunk_req = chunk;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_set_timing(cleora_ctx *c, int on)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    c->timing = on != 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_kernel_time(cleora_ctx *c, double *spmm_ms, int64_t *spmm_n, double *comb_ms,
+                       int64_t *comb_n)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    double a = 0, b = 0;
+    for (auto &p : c->ev_spmm) {
+        CLEORA_HIP(hipEventSynchronize(p.second));
+        float ms = 0;
+        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+        a += ms;
+    }
+    for (auto &p : c->ev_comb) {
+        CLEORA_HIP(hipEventSynchronize(p.second));
+        float ms = 0;
+        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+        b += ms;
+    }
+    if (spmm_ms) *spmm_ms = a;
+    if (spmm_n) *spmm_n = (int64_t)c->ev_spmm.size();
+    if (comb_ms) *comb_ms = b;
+    if (comb_n) *comb_n = (int64_t)c->ev_comb.size();
+    c->ev_spmm.clear();
+    c->ev_comb.clear();
+    c->ev_next = 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graphs,
+                       uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
+                       void *stream)
+{
+    ABI_BEGIN
+    if (!c || !graphs || !out) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (n_graphs < 1) return fail(CLEORA_E_INVAL, "n_graphs must be >= 1");
+    if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
+    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
+    check_dim(dim, dtype);
+    std::vector<int64_t> row0((size_t)n_graphs + 1, 0), eoff((size_t)n_graphs + 1, 0);
+    std::vector<uint64_t> seeds((size_t)n_graphs);
+    bool any_w = false;
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const cleora_graph &G = graphs[g];
+        check_graph_sizes(G.n_nodes, G.n_edges);
+        if (G.n_edges > 0 && (!G.src || !G.dst)) return fail(CLEORA_E_INVAL, "graph src/dst NULL");
+        if (!out[g]) return fail(CLEORA_E_INVAL, "output pointer NULL");
+        row0[g + 1] = row0[g] + G.n_nodes;
+        eoff[g + 1] = eoff[g] + G.n_edges;
+        seeds[g] = G.seed;
+        any_w = any_w || G.w != nullptr;
+    }
+    const int64_t N = row0[n_graphs], M = eoff[n_graphs];
+    check_graph_sizes(N, M);
+    DeviceGuard dg(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    // concatenated edge list with node offsets, then the ordinary build
+    const size_t ebytes = ((size_t)std::max<int64_t>(M, 1) * (any_w ? 12 : 8) + 255) / 256 * 256;
+    c->t_edges.ensure(ebytes + sizeof(int64_t) * (row0.size() + seeds.size()) + 64);
+    int32_t *osrc = c->t_edges.as<int32_t>(), *odst = osrc + std::max<int64_t>(M, 1);
+    float *ow = any_w ? reinterpret_cast<float *>(odst + std::max<int64_t>(M, 1)) : nullptr;
+    char *tail = c->t_edges.as<char>() + ebytes;
+    int64_t *d_row0 = reinterpret_cast<int64_t *>(tail);
+    uint64_t *d_seeds = reinterpret_cast<uint64_t *>(d_row0 + row0.size());
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const cleora_graph &G = graphs[g];
+        if (G.n_edges == 0) continue;
+        const unsigned blocks = (unsigned)std::min<int64_t>(cleora::ceil_div(G.n_edges, 256), 65536);
+        k_offset_edges<<<blocks, 256, 0, s>>>(G.n_edges, G.src, G.dst, G.w, G.n_nodes, row0[g],
+                                              osrc + eoff[g], odst + eoff[g],
+                                              ow ? ow + eoff[g] : nullptr);
+        CLEORA_LAUNCH_CHECK();
+    }
+    CLEORA_HIP(hipMemcpyAsync(d_row0, row0.data(), sizeof(int64_t) * row0.size(),
+                              hipMemcpyHostToDevice, s));
+    CLEORA_HIP(hipMemcpyAsync(d_seeds, seeds.data(), sizeof(uint64_t) * seeds.size(),
+                              hipMemcpyHostToDevice, s));
+    cleora::build_graph(c, N, M, osrc, odst, ow, flags, s);  // synchronises
+    setup_embedding(c, dim, dtype, s);
+    cleora::launch_init(dtype, c->E[0].p, N, dim, c->ld, d_row0, d_seeds, n_graphs, 0, s);
+    c->has_emb = true;
+    run_steps(c, k, s);
+    const size_t es = elem_size(dtype);
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const char *src = c->E[c->cur].as<char>() + (size_t)row0[g] * c->ld * es;
+        CLEORA_HIP(hipMemcpy2DAsync(out[g], (size_t)dim * es, src, (size_t)c->ld * es,
+                                    (size_t)dim * es, (size_t)graphs[g].n_nodes, hipMemcpyDefault,
+                                    s));
+    }
+    // the host vectors above must outlive the copies that read them
+    CLEORA_HIP(hipStreamSynchronize(s));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream)
+{
+    ABI_BEGIN
+    if (n < 0 || (n > 0 && !ctxs)) return fail(CLEORA_E_INVAL, "bad context list");
+    if (n == 0) return CLEORA_OK;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!ctxs[i]) return fail(CLEORA_E_INVAL, "NULL context");
+        if (!ctxs[i]->has_emb) return fail(CLEORA_E_STATE, "context without embedding");
+        if (ctxs[i]->dtype != ctxs[0]->dtype || ctxs[i]->ld != ctxs[0]->ld ||
+            ctxs[i]->device != ctxs[0]->device)
+            return fail(CLEORA_E_INVAL, "contexts differ in dim, dtype or device");
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(CLEORA_E_INVAL, "context listed twice");
+    }
+    cleora_ctx *c0 = ctxs[0];
+    DeviceGuard dg(c0->device);
+    hipStream_t s = cleora::as_stream(stream);
+    std::vector<StepDesc> tab((size_t)n);
+    int64_t waves = 0, blocks = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        tab[i] = cleora::host_desc(ctxs[i], ctxs[i]->cur);
+        tab[i].wave_begin = waves;
+        tab[i].block_begin = blocks;
+        waves += ctxs[i]->n_split + ctxs[i]->n_buckets;
+        blocks += ctxs[i]->n_long;
+    }
+    c0->multi_desc.ensure(sizeof(StepDesc) * tab.size());
+    CLEORA_HIP(hipMemcpyAsync(c0->multi_desc.p, tab.data(), sizeof(StepDesc) * tab.size(),
+                              hipMemcpyHostToDevice, s));
+    const cleora::Variant v = cleora::choose_variant(c0->dtype, c0->ld);
+    const StepDesc *d = c0->multi_desc.as<StepDesc>();
+    cleora::launch_spmm(v, d, n, waves, s);
+    if (blocks > 0) cleora::launch_combine(v, d, n, blocks, s);
+    for (int32_t i = 0; i < n; ++i) {
+        ctxs[i]->cur ^= 1;
+        ctxs[i]->iteration++;
+    }
+    // the descriptor table is host memory read by the copy above
+    CLEORA_HIP(hipStreamSynchronize(s));
+    return CLEORA_OK;
+    ABI_END
+}
+
+}  // extern "C"

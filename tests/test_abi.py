@@ -1,0 +1,77 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and its pure functions answer without a GPU."""
+
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cleora.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cleora_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2102_02302_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libcleora.so is not built (python -m paper_2102_02302_amd.build)")
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["cleora_build_csr", "cleora_init", "cleora_propagate", "cleora_embed_batch",
+                 "cleora_get_embedding", "cleora_step_multi", "cleora_last_error"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2102_02302_amd import _lib
+    names = declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(cleora_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        getattr(lib, n)
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_header_compiles_as_c():
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c",
+                        HEADER], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_footprint_is_pure_and_monotone(lib):
+    f = lib.cleora_footprint_bytes
+    a = f(1_000_000, 20_000_000, 0, 256, 0)
+    b = f(1_000_000, 20_000_000, 0, 256, 1)
+    c = f(1_000_000, 40_000_000, 0, 256, 0)
+    # two N x d float32 buffers at least (Section 4.5 memory model)
+    assert a >= 2 * 1_000_000 * 256 * 4
+    assert b < a < c
+    assert f(0, 10, 0, 256, 0) == 0 and f(10, 10, 0, 0, 0) == 0 and f(10, 10, 0, 8, 7) == 0
+
+
+def test_error_paths_without_gpu(lib):
+    import ctypes
+    from paper_2102_02302_amd import _lib
+    assert lib.cleora_create(None, 0) == _lib.E_INVAL
+    assert b"NULL" in lib.cleora_last_error()
+    assert lib.cleora_propagate(None, 1, None) == _lib.E_INVAL
+    assert lib.cleora_step_multi(None, -1, None) == _lib.E_INVAL
+    lib.cleora_destroy(None)
+    h = ctypes.c_void_p()
+    # on a machine without a GPU there is no device 0
+    import torch
+    if not torch.cuda.is_available():
+        assert lib.cleora_create(ctypes.byref(h), 0) == _lib.E_DEVICE

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, on
+the same seeded inputs, element by element.
+
+Bars: integer CSR results bit-exact; T_0 bit-exact (float32, and bfloat16
+after round-to-nearest-even); float32 embeddings within max-abs 1e-5 of the
+FP64 oracle; bfloat16-storage embeddings within max-abs 4e-3 and minimum row
+cosine 0.9999.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+BF16_MAXABS = 4e-3
+BF16_MINCOS = 0.9999
+
+
+@pytest.fixture(scope="module")
+def cl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2102_02302_amd as cl
+    cl.load()  # raises if the HIP library is missing: no fallback
+    return cl
+
+
+def gpu_embed(cl, g, dim, k, seed, dtype="f32", chunk=0, empty_keep=False):
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g, empty_keep=empty_keep)
+        if chunk:
+            ctx.set_chunk(chunk)
+        ctx.init(dim, dtype, seed)
+        ctx.propagate(k)
+        return ctx.embedding().float().cpu().numpy().astype(np.float64)
+
+
+def oracle_embed(g, dim, k, seed, empty_keep=False):
+    return oracle.embed(g, dim, k, seed, oracle.EMPTY_KEEP if empty_keep else 0)
+
+
+def zoo():
+    star = gen.Graph(20_001, np.zeros(20_000, np.int32), np.arange(1, 20_001, dtype=np.int32),
+                     None, False, "star20k")
+    return [
+        gen.erdos_renyi(3000, 15_000, 1),
+        gen.random_graph(500, 3000, 2, directed=True, weighted=True, loops=True, multi=True),
+        gen.random_graph(700, 2000, 3, directed=False, weighted=True, loops=True, multi=True),
+        gen.chung_lu(5000, 40_000, 2.1, 4),
+        gen.bipartite_zipf(3000, 500, 30_000, 1.1, 5),
+        star,
+    ]
+
+
+# ------------------------------------------------------------- init
+
+@pytest.mark.parametrize("dim", [1, 3, 37, 128, 256, 1024])
+def test_init_bitwise_f32(cl, dim):
+    g = gen.erdos_renyi(600, 1500, 9)
+    got = gpu_embed(cl, g, dim, 0, seed=123)
+    want = oracle.init(123, g.n, dim)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dim", [5, 64, 512])
+def test_init_bitwise_bf16(cl, dim):
+    import torch
+    g = gen.erdos_renyi(400, 1000, 9)
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g).init(dim, "bf16", 77)
+        got = ctx.embedding().cpu()
+    want = torch.tensor(oracle.init(77, g.n, dim), dtype=torch.float32).to(torch.bfloat16)
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16))
+
+
+# -------------------------------------------------------------- CSR
+
+@pytest.mark.parametrize("gi", range(6))
+def test_csr_matches_oracle(cl, gi):
+    g = zoo()[gi]
+    adj = oracle.build_graph(g)
+    mval, deg = oracle.transition(adj)
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g)
+        csr = {k: v.cpu().numpy() for k, v in ctx.csr().items()}
+    assert np.array_equal(csr["row_ptr"], adj.row_ptr)
+    assert np.array_equal(csr["col"], adj.col)
+    assert np.allclose(csr["deg"], deg, rtol=1e-15, atol=0)
+    if g.w is None:
+        assert np.array_equal(csr["deg"], deg)
+    assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001)
+
+
+def test_csr_long_rows_weighted(cl):
+    # one row of 40k entries (block radix sort), rows of ~5k (LDS sort),
+    # repeated weighted pairs to merge
+    rng = np.random.default_rng(8)
+    n = 50_000
+    hub = np.zeros(60_000, np.int32)
+    tgt = rng.integers(1, n, 60_000).astype(np.int32)
+    mid_src = rng.integers(1, 40, 100_000).astype(np.int32)
+    mid_dst = rng.integers(0, n, 100_000).astype(np.int32)
+    src = np.concatenate([hub, mid_src])
+    dst = np.concatenate([tgt, mid_dst])
+    w = rng.lognormal(0, 1, src.size).astype(np.float32)
+    for directed in (True, False):
+        g = gen.Graph(n, src, dst, w, directed)
+        adj = oracle.build_graph(g)
+        mval, deg = oracle.transition(adj)
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g)
+            csr = {k: v.cpu().numpy() for k, v in ctx.csr().items()}
+        assert np.array_equal(csr["row_ptr"], adj.row_ptr)
+        assert np.array_equal(csr["col"], adj.col)
+        assert np.allclose(csr["deg"], deg, rtol=1e-14, atol=0)
+        assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001 + 1e-30)
+
+
+# ------------------------------------------------------ propagation
+
+@pytest.mark.parametrize("gi", range(6))
+@pytest.mark.parametrize("dim,chunk", [(128, 0), (256, 0), (37, 16), (1024, 0), (64, 8)])
+def test_propagate_parity_f32(cl, gi, dim, chunk):
+    g = zoo()[gi]
+    got = gpu_embed(cl, g, dim, 3, seed=5, chunk=chunk)
+    want = oracle_embed(g, dim, 3, 5)
+    err = np.abs(got - want).max()
+    assert err <= F32_TOL, (g.name, dim, chunk, err)
+
+
+def test_er10k_workload_parity(cl):
+    # the small Erdos-Renyi workload in full: N=10k, 50k edges, d=128, k=4
+    g, dim, k, _ = gen.workload("er10k")
+    got = gpu_embed(cl, g, dim, k, seed=2102)
+    want = oracle_embed(g, dim, k, 2102)
+    err = np.abs(got - want).max()
+    print(f"er10k max-abs {err:.3e}")
+    assert err <= F32_TOL
+
+
+def test_empty_keep(cl):
+    g = gen.random_graph(2000, 1500, 12, directed=True)
+    for keep in (False, True):
+        got = gpu_embed(cl, g, 48, 3, seed=3, empty_keep=keep)
+        want = oracle_embed(g, 48, 3, 3, empty_keep=keep)
+        assert np.abs(got - want).max() <= F32_TOL
+
+
+def test_gpu_invariants(cl):
+    g = gen.chung_lu(20_000, 150_000, 2.1, 13)
+    adj = oracle.build_graph(g)
+    deg = np.diff(adj.row_ptr)
+    T = gpu_embed(cl, g, 256, 4, seed=1)
+    nrm = np.linalg.norm(T, axis=1)
+    assert np.all(np.abs(nrm[deg > 0] - 1) < 1e-5)
+    assert np.all(T[deg == 0] == 0)
+
+
+def test_resume_is_bitwise(cl):
+    g = gen.chung_lu(20_000, 150_000, 2.1, 14)
+    with cl.Context(0) as a, cl.Context(0) as b:
+        a.build_graph(g).init(128, "f32", 9).propagate(4)
+        b.build_graph(g).init(128, "f32", 9).propagate(1).propagate(0).propagate(3)
+        assert a.info()["iteration"] == 4 == b.info()["iteration"]
+        ea, eb = a.embedding().cpu().numpy(), b.embedding().cpu().numpy()
+    assert np.array_equal(ea, eb)
+
+
+def test_deterministic_rerun(cl):
+    g = gen.bipartite_zipf(20_000, 3000, 200_000, 1.1, 15)
+    a = gpu_embed(cl, g, 256, 4, seed=4, chunk=64)
+    b = gpu_embed(cl, g, 256, 4, seed=4, chunk=64)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------ batched
+
+def test_batch_equals_solo_bitwise(cl):
+    graphs = [gen.chung_lu(3000, 20_000, 2.1, 20), gen.erdos_renyi(500, 2000, 21),
+              gen.bipartite_zipf(2000, 300, 15_000, 1.1, 22), gen.chung_lu(8000, 60_000, 2.1, 23)]
+    seeds = [5, 6, 7, 8]
+    with cl.Context(0) as ctx:
+        outs = cl.embed_batch(ctx, graphs, 96, 4, seeds)
+        outs = [o.cpu().numpy() for o in outs]
+    for g, s, o in zip(graphs, seeds, outs):
+        solo = gpu_embed(cl, g, 96, 4, seed=s).astype(np.float32)
+        assert np.array_equal(o, solo), g.name
+        assert np.abs(o - oracle_embed(g, 96, 4, s)).max() <= F32_TOL
+
+
+def test_step_multi_equals_solo_bitwise(cl):
+    graphs = [gen.chung_lu(4000, 30_000, 2.1, 30), gen.erdos_renyi(900, 4000, 31),
+              gen.chung_lu(12_000, 90_000, 2.1, 32)]
+    ctxs = [cl.Context(0) for _ in graphs]
+    try:
+        for c, g, s in zip(ctxs, graphs, [1, 2, 3]):
+            c.build_graph(g).init(128, "f32", s)
+        ctxs[0].propagate(1)  # requests at different iterations share a step
+        for _ in range(3):
+            cl.step_multi(ctxs)
+        cl.step_multi(ctxs[1:])
+        got = [c.embedding().cpu().numpy() for c in ctxs]
+        its = [c.info()["iteration"] for c in ctxs]
+    finally:
+        for c in ctxs:
+            c.close()
+    assert its == [4, 4, 4]
+    for g, s, o in zip(graphs, [1, 2, 3], got):
+        assert np.array_equal(o, gpu_embed(cl, g, 128, 4, seed=s).astype(np.float32))
+
+
+# --------------------------------------------------------------- bf16
+
+def bf16_report(got, want):
+    err = np.abs(got - want).max()
+    nz = np.linalg.norm(want, axis=1) > 0
+    cos = (got[nz] * want[nz]).sum(1) / (np.linalg.norm(got[nz], axis=1) *
+                                         np.linalg.norm(want[nz], axis=1))
+    return float(err), float(cos.min())
+
+
+@pytest.mark.parametrize("gi", [0, 3, 4])
+def test_bf16_error_bound(cl, gi):
+    g = zoo()[gi]
+    got = gpu_embed(cl, g, 256, 4, seed=6, dtype="bf16")
+    want = oracle_embed(g, 256, 4, 6)
+    err, cmin = bf16_report(got, want)
+    print(f"bf16 {g.name}: max-abs {err:.3e} min-cos {cmin:.7f}")
+    assert err <= BF16_MAXABS and cmin >= BF16_MINCOS
+
+
+# ------------------------------------------------------------- errors
+
+def test_invalid_inputs(cl):
+    from paper_2102_02302_amd import _lib
+    with cl.Context(0) as ctx:
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.build_csr(10, [0, 11], [1, 2])
+        assert e.value.code == _lib.E_INPUT
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.build_csr(10, [0, 1], [1, 2], w=[1.0, -1.0])
+        assert e.value.code == _lib.E_INPUT
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.build_csr(10, [0, 1], [1, 2], w=[1.0, math.inf])
+        assert e.value.code == _lib.E_INPUT
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.init(16, "f32", 0)  # no graph after a failed build
+        assert e.value.code == _lib.E_STATE
+        ctx.build_csr(10, [0, 1], [1, 2])
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.init(0, "f32", 0)
+        assert e.value.code == _lib.E_INVAL
+        with pytest.raises(cl.CleoraError) as e:
+            ctx.propagate(1)
+        assert e.value.code == _lib.E_STATE
+        ctx.init(16, "f32", 0)
+        with pytest.raises(cl.CleoraError):
+            ctx.propagate(-1)
+        ctx.propagate(2)
+        assert ctx.info()["iteration"] == 2
+
+
+def test_empty_graph_and_tiny(cl):
+    g = gen.Graph(5, np.zeros(0, np.int32), np.zeros(0, np.int32), None, False)
+    T = gpu_embed(cl, g, 8, 2, seed=1)
+    assert np.all(T == 0)
+    T = gpu_embed(cl, g, 8, 2, seed=1, empty_keep=True)
+    assert np.abs(T - oracle_embed(g, 8, 2, 1, empty_keep=True)).max() <= F32_TOL
+    g1 = gen.Graph(1, np.zeros(1, np.int32), np.zeros(1, np.int32), None, False)  # one loop
+    assert np.abs(gpu_embed(cl, g1, 3, 3, seed=2) - oracle_embed(g1, 3, 3, 2)).max() <= F32_TOL
