@@ -1,0 +1,218 @@
+"""Benchmark of the Cleora propagation hot path on one MI355X.
+
+One step = the whole path on one synthetic graph whose edge list is already
+in HBM: build M = D^-1 A (CSR, FP64 row sums), initialise T_0, run k
+iterations of multiply + row L2 normalisation.  Throughput is edge-dims per
+second: k * nnz * d / step time (nnz = stored entries of M).
+
+Prints one JSON line.  The roofline object describes the fused SpMM +
+normalise kernel (HBM-bound): its algorithmic bytes per launch
+
+    nnz * (4 + 4)                  column index + M value per entry
+  + nnz * d * s                    one gathered row of T per entry
+  + (N - n_split_rows) * d * s     one written row of T per row it finishes
+
+divided by its average launch time, measured with HIP events on the launch
+stream during the timed steps.  ``traffic`` is the measured HBM traffic per
+launch from the committed rocprofv3 counter summary, when that summary was
+taken on the current kernel source.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GEdge-dims/s per iteration (nnz·d/s) + % HBM peak; p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2102_02302_amd", "csrc", "propagate.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "spmm_norm_{workload}_{dtype}_pmc.json")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chunglu1m",
+                    help="er10k | chunglu1m | chunglu10m | bipartite6m")
+    ap.add_argument("--dtype", default=None, help="override the workload's dtype (f32|bf16)")
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="launch one plain device copy of this many GiB first "
+                         "(reference kernel for HBM counter scaling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                                   "(the multi-GPU column split is a design, not code)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2102_02302_amd as cl
+
+    spec = gen.WORKLOADS[args.workload]
+    dim = spec["dim"]
+    k = args.k if args.k is not None else spec["k"]
+    dtype = args.dtype or spec["dtype"]
+    esz = 2 if dtype == "bf16" else 4
+
+    t0 = time.time()
+    g = spec["make"]()
+    gen_s = time.time() - t0
+    print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", flush=True)
+
+    dev = torch.device("cuda", 0)
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * (1 << 30)) // 4
+        a = torch.ones(nb, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    src = torch.as_tensor(g.src).to(dev)
+    dst = torch.as_tensor(g.dst).to(dev)
+    w = torch.as_tensor(g.w).to(dev) if g.w is not None else None
+    torch.cuda.synchronize()
+
+    ctx = cl.Context(0)
+    if args.chunk:
+        ctx.set_chunk(args.chunk)
+
+    def step():
+        ctx.build_csr(g.n, src, dst, w, directed=g.directed)
+        ctx.init(dim, dtype, seed=2102)
+        ctx.propagate(k)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.kernel_time()  # reset
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ctx.set_timing(False)
+    kt = ctx.kernel_time()
+    info = ctx.info()
+    nnz, n = info["nnz"], info["n"]
+
+    # separate measurement of the phases (not part of the timed steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    ctx.build_csr(g.n, src, dst, w, directed=g.directed)
+    torch.cuda.synchronize()
+    tb2 = time.perf_counter()
+    ctx.init(dim, dtype, seed=2102)
+    torch.cuda.synchronize()
+    tb3 = time.perf_counter()
+    ctx.propagate(k)
+    torch.cuda.synchronize()
+    tb4 = time.perf_counter()
+    phase = {"build_ms": (tb2 - tb) * 1e3, "init_ms": (tb3 - tb2) * 1e3,
+             "propagate_ms": (tb4 - tb3) * 1e3}
+
+    ms_per_step = (t_end - t_start) * 1e3 / args.steps
+    edge_dims = float(k) * nnz * dim
+    value = edge_dims / (ms_per_step * 1e-3) / 1e9
+
+    # dominant kernel: fused SpMM + normalise
+    spmm_ms = kt["spmm_ms"] / max(kt["spmm_launches"], 1)
+    comb_ms = kt["combine_ms"] / max(kt["combine_launches"], 1) if kt["combine_launches"] else 0.0
+    sched = ctx.schedule()
+    split_rows = sched["split_rows"]
+    spmm_bytes = nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz
+    achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
+    traffic = _traffic(args.workload, dtype)
+    iter_ms = spmm_ms + comb_ms
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_spmm_norm", "bytes_per_launch": int(spmm_bytes),
+                "avg_launch_ms": round(spmm_ms, 4), "launches": kt["spmm_launches"],
+                "combine_avg_ms": round(comb_ms, 4), "schedule": sched}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GEdge-dims/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "desc": spec["desc"], "n_nodes": n,
+                   "n_edges": g.m, "nnz": nnz, "dim": dim, "k": k,
+                   "step": "build CSR + FP64 row sums + init T_0 + k iterations",
+                   "parallelism": "single GPU"},
+        "propagate_only": {"ms_per_iteration": round(iter_ms, 4),
+                           "gedge_dims_per_s": round(nnz * dim / (iter_ms * 1e-3) / 1e9, 2),
+                           "model_bytes_per_iteration": int(nnz * 8 + nnz * dim * esz + n * dim * esz),
+                           "hbm_frac_model": round((nnz * 8 + nnz * dim * esz + n * dim * esz)
+                                                   / (iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "phases_ms": {kk: round(v, 3) for kk, v in phase.items()},
+        "roofline": roofline,
+    }
+    ctx.close()
+    del ctx
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(g, dim, k)
+    print(json.dumps(out), flush=True)
+
+
+def _traffic(workload: str, dtype: str):
+    path = PMC_SUMMARY.format(workload=workload, dtype=dtype)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        s = json.load(f)
+    if s.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return s.get("hbm_bytes_per_launch")
+
+
+def _cpu_baseline(g, dim: int, k: int) -> dict:
+    """The FP64 oracle on the host cores: the same whole path (adjacency,
+    M, T_0, k iterations) on the same graph, timed once."""
+    import oracle
+    threads = oracle.get_threads()
+    t0 = time.perf_counter()
+    adj = oracle.build_graph(g)
+    mval, _ = oracle.transition(adj)
+    T0 = oracle.init(2102, g.n, dim)
+    oracle.propagate(adj, mval, T0, k)
+    dt = time.perf_counter() - t0
+    return {"value": round(k * adj.nnz * dim / dt / 1e9, 4), "unit": "GEdge-dims/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"whole path on the full graph (n={g.n}, nnz={adj.nnz}, d={dim}, k={k}), "
+                      f"FP64, {dt:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -128,6 +128,13 @@ int cleora_get_csr(cleora_ctx *ctx, int64_t *row_ptr, int32_t *col, float *val, 
 int cleora_info(cleora_ctx *ctx, int64_t *n_nodes, int64_t *nnz, int32_t *dim, int32_t *dtype,
                 int32_t *iteration);
 
+/* Propagation schedule planned by the last cleora_init: entries per work
+ * item, number of split chunks, rows split into chunks (finished by the
+ * combine step), packed work items.  Any pointer may be NULL.
+ * Errors: E_STATE (no embedding). */
+int cleora_schedule_info(cleora_ctx *ctx, int32_t *chunk, int64_t *n_split_chunks,
+                         int64_t *n_split_rows, int64_t *n_packed_items);
+
 /* Wait for the stream.  Errors: E_DEVICE. */
 int cleora_sync(cleora_ctx *ctx, void *stream);
 

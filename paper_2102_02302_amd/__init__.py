@@ -141,6 +141,14 @@ class Context:
         return {"n": n.value, "nnz": nnz.value, "dim": dim.value, "dtype": dt.value,
                 "iteration": it.value}
 
+    def schedule(self) -> dict:
+        chunk = ctypes.c_int32()
+        ns, nl, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.cleora_schedule_info(self._h, ctypes.byref(chunk), ctypes.byref(ns),
+                                                  ctypes.byref(nl), ctypes.byref(nb)))
+        return {"chunk": chunk.value, "split_chunks": ns.value, "split_rows": nl.value,
+                "packed_items": nb.value}
+
     def embedding(self, dtype=None, stream=None):
         """Copy of the current N x dim embedding as a device tensor."""
         torch = _torch()

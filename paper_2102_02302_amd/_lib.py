@@ -24,7 +24,7 @@ _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
-    "cleora_get_csr", "cleora_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
+    "cleora_get_csr", "cleora_info", "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
     "cleora_kernel_time", "cleora_embed_batch", "cleora_step_multi", "cleora_last_error",
 ]
 
@@ -67,6 +67,8 @@ def load() -> ctypes.CDLL:
         "cleora_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
                                        ctypes.POINTER(i32)]),
+        "cleora_schedule_info": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "cleora_sync": (ctypes.c_int, [p, p]),
         "cleora_set_chunk": (ctypes.c_int, [p, i32]),
         "cleora_set_timing": (ctypes.c_int, [p, ctypes.c_int]),

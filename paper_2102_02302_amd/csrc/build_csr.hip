@@ -2,16 +2,19 @@
 // the number of a->b edges or the sum of their weights, M_ab = e_ab/deg(a);
 // undirected edges are stored in both directions, Section 4.5).
 //
-// Pipeline (all on the caller's stream, one host synchronisation at the end):
-//   count degrees -> scan -> scatter (col[, weight]) into rows ->
-//   sort every row by (col, weight) -> mark the first entry of each run of
-//   equal columns -> scan -> compact (e_ab summed in float64) ->
-//   deg(a) in float64 -> M values rounded to float32.
-// Rows are sorted by three kernels chosen by length: a wave-wide bitonic
-// network (<= 64 entries), an LDS bitonic network (<= 64 KiB of keys) and a
-// block-wide stable LSD radix sort over global memory (longer hub rows).
-// The sort key includes the weight bits, so the merged sums (and everything
-// after them) do not depend on the order the atomics placed entries in.
+// Pipeline (caller's stream, one host synchronisation at the end):
+//   1. one 64-bit key per stored entry, key = row << cb | col (cb = bits of
+//      N-1); a loop's second copy and invalid edges get a key above every
+//      valid one; optional float32 weight as payload;
+//   2. stable LSD radix sort of the keys (8-bit digits, reduce-then-scan:
+//      per-tile digit counts, one device scan, stable scatter through LDS) --
+//      no global atomics, so hub rows cost no more than other rows, and
+//      repeated (a, b) pairs keep their input order;
+//   3. mark the first entry of each run of equal keys, scan, compact: one
+//      merged entry per pair with e_ab summed in float64 in input order;
+//   4. row pointers by binary search over the merged keys;
+//   5. deg(a) = sum_b e_ab in float64 and M_ab = e_ab / deg(a) in float32
+//      (one wave per row, one block per long row, fixed reduction order).
 #include "internal.hpp"
 
 #include <algorithm>
@@ -22,297 +25,243 @@ namespace {
 
 constexpr uint32_t ERR_ID = 1u, ERR_WEIGHT = 2u;
 
-// Sort keys: uint32 = column (unweighted graphs), uint64 = column << 32 |
-// float bits of the weight (positive floats order like their bit patterns).
-template <typename K>
-__device__ __forceinline__ int32_t key_col(K k)
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block and pass
+constexpr int LONG_ROW = 4096;                  // rows summed by a whole block
+
+__device__ __forceinline__ bool weight_ok(float x)
 {
-    if constexpr (sizeof(K) == 8) return (int32_t)(k >> 32);
-    else return (int32_t)k;
-}
-template <typename K>
-__device__ __forceinline__ double key_weight(K k)
-{
-    if constexpr (sizeof(K) == 8) return (double)__uint_as_float((uint32_t)(k & 0xffffffffu));
-    else return 1.0;
-}
-template <typename K>
-__device__ __forceinline__ K make_key(int32_t col, const float *w, int64_t e)
-{
-    if constexpr (sizeof(K) == 8)
-        return ((uint64_t)(uint32_t)col << 32) | (uint64_t)__float_as_uint(w[e]);
-    else
-        return (uint32_t)col;
+    return x > 0.0f && x <= 3.402823466e38f;  // finite and positive
 }
 
-__device__ __forceinline__ bool edge_ok(int64_t e, int64_t n, const int32_t *src,
-                                        const int32_t *dst, const float *w, uint32_t *err)
+// Keys of the stored entries: entry 2e is edge e as given, entry 2e+1 its
+// reverse (undirected graphs); directed graphs use entry e only.
+__global__ void k_make_keys(int64_t m, int64_t n, const int32_t *__restrict__ src,
+                            const int32_t *__restrict__ dst, const float *__restrict__ w,
+                            int directed, int cb, uint64_t invalid_key,
+                            uint64_t *__restrict__ keys, float *__restrict__ wout,
+                            uint32_t *err, unsigned long long *n_valid)
 {
-    int32_t a = src[e], b = dst[e];
-    if (a < 0 || a >= n || b < 0 || b >= n) {
-        atomicOr(err, ERR_ID);
-        return false;
-    }
-    if (w) {
-        float x = w[e];
-        if (!(x > 0.0f && x <= 3.402823466e38f)) {  // finite and positive
-            atomicOr(err, ERR_WEIGHT);
-            return false;
-        }
-    }
-    return true;
-}
-
-__global__ void k_count(int64_t m, int64_t n, const int32_t *__restrict__ src,
-                        const int32_t *__restrict__ dst, const float *__restrict__ w,
-                        int directed, int32_t *__restrict__ cnt, uint32_t *err)
-{
+    __shared__ unsigned long long block_valid;
+    if (threadIdx.x == 0) block_valid = 0;
+    __syncthreads();
+    unsigned long long mine = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
-        if (!edge_ok(e, n, src, dst, w, err)) continue;
-        int32_t a = src[e], b = dst[e];
-        atomicAdd(&cnt[a], 1);
-        if (!directed && a != b) atomicAdd(&cnt[b], 1);
-    }
-}
-
-template <typename K>
-__global__ void k_scatter(int64_t m, int64_t n, const int32_t *__restrict__ src,
-                          const int32_t *__restrict__ dst, const float *__restrict__ w,
-                          int directed, const int64_t *__restrict__ off,
-                          int32_t *__restrict__ cursor, K *__restrict__ keys, uint32_t *err)
-{
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int32_t a = src[e], b = dst[e];
+        const int32_t a = src[e], b = dst[e];
         bool ok = a >= 0 && a < n && b >= 0 && b < n;
-        if (ok && w) ok = w[e] > 0.0f && w[e] <= 3.402823466e38f;
-        if (!ok) continue;  // already flagged by k_count
-        int64_t p = off[a] + atomicAdd(&cursor[a], 1);
-        keys[p] = make_key<K>(b, w, e);
-        if (!directed && a != b) {
-            int64_t q = off[b] + atomicAdd(&cursor[b], 1);
-            keys[q] = make_key<K>(a, w, e);
-        }
-    }
-}
-
-// Rows of 2..64 entries: one wave, one entry per lane, bitonic network.
-template <typename K>
-__global__ __launch_bounds__(256) void k_sort_small(int64_t n, const int64_t *__restrict__ off,
-                                                    K *__restrict__ keys)
-{
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= n) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t lo = off[row], len = off[row + 1] - lo;
-    if (len < 2 || len > 64) return;
-    K key = lane < len ? keys[lo + lane] : ~K(0);
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            K other = __shfl_xor(key, j, WAVE);
-            bool asc = (lane & k) == 0, lower = (lane & j) == 0;
-            key = (asc == lower) ? (key < other ? key : other) : (key < other ? other : key);
-        }
-    }
-    if (lane < len) keys[lo + lane] = key;
-}
-
-__global__ void k_classify(int64_t n, const int64_t *__restrict__ off, int64_t mid_cap,
-                           int32_t *__restrict__ mid_list, int32_t *__restrict__ big_list,
-                           int32_t *counts)
-{
-    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n;
-         row += (int64_t)gridDim.x * blockDim.x) {
-        int64_t len = off[row + 1] - off[row];
-        if (len > 64 && len <= mid_cap) mid_list[atomicAdd(&counts[0], 1)] = (int32_t)row;
-        else if (len > mid_cap) big_list[atomicAdd(&counts[1], 1)] = (int32_t)row;
-    }
-}
-
-// Rows of 65..CAP entries: one block, bitonic network in LDS.
-template <typename K, int CAP>
-__global__ __launch_bounds__(256) void k_sort_mid(const int64_t *__restrict__ off,
-                                                  K *__restrict__ keys,
-                                                  const int32_t *__restrict__ list,
-                                                  const int32_t *__restrict__ count)
-{
-    __shared__ K s[CAP];
-    const int cnt = *count;
-    for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
-        const int64_t row = list[li];
-        const int64_t lo = off[row];
-        const int len = (int)(off[row + 1] - lo);
-        int P = 128;
-        while (P < len) P <<= 1;
-        for (int i = threadIdx.x; i < P; i += blockDim.x) s[i] = i < len ? keys[lo + i] : ~K(0);
-        __syncthreads();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = threadIdx.x; i < P / 2; i += blockDim.x) {
-                    int a = 2 * i - (i & (j - 1)), b = a + j;
-                    bool asc = (a & k) == 0;
-                    K x = s[a], y = s[b];
-                    if ((x > y) == asc) {
-                        s[a] = y;
-                        s[b] = x;
-                    }
-                }
-                __syncthreads();
+        if (!ok) atomicOr(err, ERR_ID);
+        float x = 1.0f;
+        if (w) {
+            x = w[e];
+            if (ok && !weight_ok(x)) {
+                atomicOr(err, ERR_WEIGHT);
+                ok = false;
             }
         }
-        for (int i = threadIdx.x; i < len; i += blockDim.x) keys[lo + i] = s[i];
-        __syncthreads();
+        const uint64_t fwd = ok ? ((uint64_t)a << cb) | (uint64_t)b : invalid_key;
+        if (directed) {
+            keys[e] = fwd;
+            if (wout) wout[e] = x;
+            mine += ok ? 1 : 0;
+        } else {
+            const bool rev_ok = ok && a != b;  // a loop is stored once
+            keys[2 * e] = fwd;
+            keys[2 * e + 1] = rev_ok ? ((uint64_t)b << cb) | (uint64_t)a : invalid_key;
+            if (wout) {
+                wout[2 * e] = x;
+                wout[2 * e + 1] = x;
+            }
+            mine += (ok ? 1 : 0) + (rev_ok ? 1 : 0);
+        }
     }
+    mine = wave_sum(mine);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&block_valid, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_valid) atomicAdd(n_valid, block_valid);
 }
 
-// Rows longer than the LDS network: one block of 1024 threads runs a stable
-// LSD radix sort (8-bit digits) over the row in global memory, ping-ponging
-// with tmp.  Low digits first: the weight bits (uint64 keys), then the column.
-template <typename K>
-__global__ __launch_bounds__(1024) void k_sort_big(const int64_t *__restrict__ off,
-                                                   K *__restrict__ keys, K *__restrict__ tmp,
-                                                   const int32_t *__restrict__ list,
-                                                   const int32_t *__restrict__ count,
-                                                   int col_passes)
+// Radix pass, step 1: count[d * nblk + b] = keys of tile b with digit d.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restrict__ keys,
+                                                         int64_t n, int shift, int64_t nblk,
+                                                         int32_t *__restrict__ count)
 {
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t tcount[256];
-    __shared__ uint16_t wcnt[16][256];
+    __shared__ uint32_t h[RS_THREADS / WAVE][256];
+    const int t = threadIdx.x, w = t >> 6;
+    for (int i = t; i < (RS_THREADS / WAVE) * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * RS_THREADS + t;
+        if (idx < n) atomicAdd(&h[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t s = 0;
+    for (int q = 0; q < RS_THREADS / WAVE; ++q) s += h[q][t];
+    count[(int64_t)t * nblk + blockIdx.x] = (int32_t)s;
+}
+
+// Radix pass, step 3: stable scatter.  Keys of the tile are ranked in input
+// order (rounds of 256; within a round by wave, then lane), staged in LDS in
+// digit order, and written out run by run.
+template <bool PAYLOAD>
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const float *__restrict__ pin, int64_t n, int shift,
+    int64_t nblk, const int64_t *__restrict__ offs, uint64_t *__restrict__ kout,
+    float *__restrict__ pout)
+{
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ float sp[PAYLOAD ? RS_TILE : 1];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint16_t wc[RS_THREADS / WAVE][256];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wpass = sizeof(K) == 8 ? 4 : 0;
-    const int npass = wpass + col_passes;
-    const int cnt = *count;
-    for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
-        const int64_t row = list[li];
-        const int64_t lo = off[row];
-        const int64_t len = off[row + 1] - lo;
-        K *from = keys + lo, *to = tmp + lo;
-        for (int p = 0; p < npass; ++p) {
-            const int shift = p < wpass ? 8 * p : (sizeof(K) == 8 ? 32 : 0) + 8 * (p - wpass);
-            if (t < 256) hist[t] = 0;
-            __syncthreads();
-            for (int64_t i = t; i < len; i += 1024)
-                atomicAdd(&hist[(uint32_t)(from[i] >> shift) & 255u], 1u);
-            __syncthreads();
-            if (t == 0) {
-                uint32_t s = 0;
-                for (int d = 0; d < 256; ++d) {
-                    base[d] = s;
-                    s += hist[d];
-                }
-            }
-            __syncthreads();
-            for (int64_t t0 = 0; t0 < len; t0 += 1024) {
-                const int64_t i = t0 + t;
-                const bool valid = i < len;
-                const K key = valid ? from[i] : K(0);
-                const uint32_t dg = valid ? ((uint32_t)(key >> shift) & 255u) : 0u;
-                for (int x = t; x < 16 * 256; x += 1024) (&wcnt[0][0])[x] = 0;
-                __syncthreads();
-                uint64_t peers = __ballot(valid);
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    run[t] = 0;
+    uint64_t key[RS_ITEMS];
+    uint32_t rank[RS_ITEMS];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const bool bit = (dg >> b) & 1u;
-                    const uint64_t m = __ballot(bit);
-                    peers &= bit ? m : ~m;
-                }
-                const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-                if (valid && rank == 0) wcnt[w][dg] = (uint16_t)__popcll(peers);
-                __syncthreads();
-                if (t < 256) {
-                    uint32_t s = 0;
-                    for (int x = 0; x < 16; ++x) {
-                        uint32_t c = wcnt[x][t];
-                        wcnt[x][t] = (uint16_t)s;
-                        s += c;
-                    }
-                    tcount[t] = s;
-                }
-                __syncthreads();
-                if (valid) to[base[dg] + wcnt[w][dg] + rank] = key;
-                __syncthreads();
-                if (t < 256) base[t] += tcount[t];
-                __syncthreads();
-            }
-            K *sw = from;
-            from = to;
-            to = sw;
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * RS_THREADS + t;
+        const bool valid = idx < n;
+        key[i] = valid ? kin[idx] : 0;
+        const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+        for (int q = t; q < (RS_THREADS / WAVE) * 256; q += RS_THREADS) (&wc[0][0])[q] = 0;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t mk = __ballot(bit);
+            peers &= bit ? mk : ~mk;
         }
-        if (from != keys + lo)
-            for (int64_t i = t; i < len; i += 1024) keys[lo + i] = from[i];
+        const uint32_t inwave = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        if (valid && inwave == 0) wc[w][d] = (uint16_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t s = run[t];
+            for (int q = 0; q < RS_THREADS / WAVE; ++q) {
+                const uint32_t c = wc[q][t];
+                wc[q][t] = (uint16_t)s;
+                s += c;
+            }
+            run[t] = s;
+        }
+        __syncthreads();
+        rank[i] = valid ? (uint32_t)wc[w][d] + inwave : 0xffffffffu;
         __syncthreads();
     }
-}
-
-// head[i] = 1 for the first entry of each run of equal columns in a row.
-template <typename K>
-__global__ void k_mark_heads(int64_t total_ub, const int64_t *__restrict__ total_p,
-                             const K *__restrict__ keys, uint8_t *__restrict__ head)
-{
-    const int64_t total = *total_p;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total_ub;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        uint8_t h = 0;
-        if (i < total) h = (i == 0 || key_col(keys[i]) != key_col(keys[i - 1])) ? 1 : 0;
-        head[i] = h;
+    // local digit starts: exclusive scan of run[] (256 entries, one wave)
+    if (w == 0) {
+        uint32_t v[4], tot = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = run[lane * 4 + q];
+            tot += v[q];
+        }
+        uint32_t x = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t s = x - tot;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            dstart[lane * 4 + q] = s;
+            s += v[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        if (rank[i] == 0xffffffffu) continue;
+        const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
+        const uint32_t lp = dstart[d] + rank[i];
+        sk[lp] = key[i];
+        if constexpr (PAYLOAD) sp[lp] = pin[base + i * RS_THREADS + t];
+    }
+    __syncthreads();
+    const int64_t cnt = min((int64_t)RS_TILE, n - base);
+    for (int j = t; j < cnt; j += RS_THREADS) {
+        const uint64_t k = sk[j];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const int64_t g = offs[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        kout[g] = k;
+        if constexpr (PAYLOAD) pout[g] = sp[j];
     }
 }
 
-__global__ void k_mark_row_starts(int64_t n, const int64_t *__restrict__ off,
-                                  uint8_t *__restrict__ head)
+// head[i] = 1 for the first entry of each run of equal keys among the
+// n_valid sorted valid entries (0 beyond).
+__global__ void k_mark_heads(int64_t total, const unsigned long long *__restrict__ n_valid,
+                             const uint64_t *__restrict__ keys, uint8_t *__restrict__ head)
 {
-    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row < n;
-         row += (int64_t)gridDim.x * blockDim.x)
-        if (off[row + 1] > off[row]) head[off[row]] = 1;
+    const int64_t nv = (int64_t)*n_valid;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        head[i] = (i < nv && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
 }
 
-// One merged entry per run: its column and e_ab (count or weight sum, float64).
-template <typename K>
-__global__ void k_compact(int64_t total_ub, const int64_t *__restrict__ total_p,
-                          const K *__restrict__ keys, const uint8_t *__restrict__ head,
-                          const int64_t *__restrict__ pos, int32_t *__restrict__ col_u,
-                          double *__restrict__ e_u)
+// One merged entry per run: key, column and e_ab (count or float64 sum of
+// the run's weights in input order).
+__global__ void k_compact(int64_t total, const unsigned long long *__restrict__ n_valid,
+                          const uint64_t *__restrict__ keys, const float *__restrict__ wts,
+                          const uint8_t *__restrict__ head, const int64_t *__restrict__ pos,
+                          uint64_t cmask, uint64_t *__restrict__ ukeys,
+                          int32_t *__restrict__ col_u, double *__restrict__ e_u)
 {
-    const int64_t total = *total_p;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+    const int64_t nv = (int64_t)*n_valid;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (!head[i]) continue;
         const int64_t u = pos[i];
-        col_u[u] = key_col(keys[i]);
-        double s = key_weight(keys[i]);
-        for (int64_t j = i + 1; j < total && !head[j]; ++j) s += key_weight(keys[j]);
+        ukeys[u] = keys[i];
+        col_u[u] = (int32_t)(keys[i] & cmask);
+        double s = wts ? (double)wts[i] : 1.0;
+        for (int64_t j = i + 1; j < nv && !head[j]; ++j) s += wts ? (double)wts[j] : 1.0;
         e_u[u] = s;
     }
-    (void)total_ub;
+    (void)total;
 }
 
-__global__ void k_rowptr(int64_t n, const int64_t *__restrict__ off,
-                         const int64_t *__restrict__ pos, int64_t *__restrict__ rp)
+// rp[a] = first merged entry whose row is >= a.
+__global__ void k_rowptr_search(int64_t n, const int64_t *__restrict__ nnz_p,
+                                const uint64_t *__restrict__ ukeys, int cb,
+                                int64_t *__restrict__ rp)
 {
+    const int64_t nnz = *nnz_p;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a <= n;
-         a += (int64_t)gridDim.x * blockDim.x)
-        rp[a] = pos[off[a]];
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t target = (uint64_t)a << cb;
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ukeys[mid] >= target) hi = mid;
+            else lo = mid + 1;
+        }
+        rp[a] = lo;
+    }
 }
 
-// deg(a) = sum_b e_ab in float64 and M_ab = e_ab / deg(a) rounded to float32.
-// One wave per row (rows whose unmerged length is at most mid_cap); the
-// per-lane partial sums are combined in a fixed butterfly order.
-__global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *__restrict__ off,
-                                                     int64_t mid_cap,
-                                                     const int64_t *__restrict__ rp,
+// deg(a) and M values; rows longer than LONG_ROW are listed for the block
+// kernel.  Per-lane partial sums are combined in a fixed butterfly order.
+__global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *__restrict__ rp,
                                                      const double *__restrict__ e_u,
                                                      float *__restrict__ val,
-                                                     double *__restrict__ deg)
+                                                     double *__restrict__ deg,
+                                                     int32_t *__restrict__ long_list,
+                                                     int32_t *__restrict__ long_count)
 {
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (row >= n) return;
-    if (off[row + 1] - off[row] > mid_cap) return;
     const int lane = threadIdx.x & 63;
     const int64_t lo = rp[row], hi = rp[row + 1];
+    if (hi - lo > LONG_ROW) {
+        if (lane == 0) long_list[atomicAdd(long_count, 1)] = (int32_t)row;
+        return;
+    }
     double s = 0.0;
     for (int64_t j = lo + lane; j < hi; j += 64) s += e_u[j];
     s = wave_sum(s);
@@ -320,7 +269,6 @@ __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *_
     for (int64_t j = lo + lane; j < hi; j += 64) val[j] = (float)(e_u[j] / s);
 }
 
-// Same for the long rows: one block of 1024 threads per row.
 __global__ __launch_bounds__(1024) void k_rowsum_block(const int32_t *__restrict__ list,
                                                        const int32_t *__restrict__ count,
                                                        const int64_t *__restrict__ rp,
@@ -358,97 +306,11 @@ unsigned grid_for(int64_t items, int threads, int64_t cap = 1 << 20)
     return (unsigned)std::min<int64_t>(g, cap);
 }
 
-template <typename K>
-void build_typed(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                 const float *w, uint32_t flags, hipStream_t s)
+int bits_for(int64_t n)
 {
-    const int directed = (flags & CLEORA_DIRECTED) ? 1 : 0;
-    const int64_t total_ub = directed ? m : 2 * m;
-    constexpr int64_t MID_CAP = 65536 / sizeof(K);
-
-    c->t_cnt.ensure(sizeof(int32_t) * 2 * (size_t)n);
-    c->t_off.ensure(sizeof(int64_t) * ((size_t)n + 1));
-    c->t_keys.ensure(sizeof(K) * (size_t)std::max<int64_t>(total_ub, 1));
-    c->t_tmp.ensure(sizeof(K) * (size_t)std::max<int64_t>(total_ub, 1));
-    c->t_head.ensure((size_t)std::max<int64_t>(total_ub, 1));
-    c->t_pos.ensure(sizeof(int64_t) * ((size_t)total_ub + 1));
-    c->t_esum.ensure(sizeof(double) * (size_t)std::max<int64_t>(total_ub, 1));
-    c->t_lists.ensure(sizeof(int32_t) * 2 * (size_t)n);
-    c->t_scan.ensure(sizeof(int64_t) * scan_workspace_elems(std::max<int64_t>(n + 1, total_ub + 1)));
-    c->rp.ensure(sizeof(int64_t) * ((size_t)n + 1));
-    c->col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(total_ub, 1));
-    c->val.ensure(sizeof(float) * (size_t)std::max<int64_t>(total_ub, 1));
-    c->deg.ensure(sizeof(double) * (size_t)n);
-
-    int32_t *cnt = c->t_cnt.as<int32_t>(), *cursor = cnt + n;
-    int64_t *off = c->t_off.as<int64_t>();
-    K *keys = c->t_keys.as<K>(), *tmp = c->t_tmp.as<K>();
-    uint8_t *head = c->t_head.as<uint8_t>();
-    int64_t *pos = c->t_pos.as<int64_t>(), *ws = c->t_scan.as<int64_t>();
-    double *esum = c->t_esum.as<double>();
-    int32_t *mid_list = c->t_lists.as<int32_t>(), *big_list = mid_list + n;
-    // t_small: [0] error word, [1] two int32 list counters
-    int64_t *small = c->t_small.as<int64_t>();
-    uint32_t *err = reinterpret_cast<uint32_t *>(small);
-    int32_t *counts = reinterpret_cast<int32_t *>(small + 1);
-
-    CLEORA_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (size_t)n, s));
-    CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
-
-    const unsigned ge = grid_for(m, 256, 65536);
-    if (m > 0) {
-        k_count<<<ge, 256, 0, s>>>(m, n, src, dst, w, directed, cnt, err);
-        CLEORA_LAUNCH_CHECK();
-    }
-    exclusive_scan(cnt, n, off, ws, s);
-    if (m > 0) {
-        k_scatter<K><<<ge, 256, 0, s>>>(m, n, src, dst, w, directed, off, cursor, keys, err);
-        CLEORA_LAUNCH_CHECK();
-    }
-    // sort rows
-    k_sort_small<K><<<(unsigned)ceil_div(n, 4), 256, 0, s>>>(n, off, keys);
-    CLEORA_LAUNCH_CHECK();
-    k_classify<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, off, MID_CAP, mid_list, big_list,
-                                                        counts);
-    CLEORA_LAUNCH_CHECK();
-    k_sort_mid<K, (int)MID_CAP><<<(unsigned)std::min<int64_t>(std::max<int64_t>(n, 1), 8192), 256,
-                                   0, s>>>(off, keys, mid_list, counts);
-    CLEORA_LAUNCH_CHECK();
-    int col_bits = 0;
-    while (col_bits < 31 && ((int64_t)1 << col_bits) < n) ++col_bits;
-    const int col_passes = std::max(1, (col_bits + 7) / 8);
-    k_sort_big<K><<<512, 1024, 0, s>>>(off, keys, tmp, big_list, counts + 1, col_passes);
-    CLEORA_LAUNCH_CHECK();
-    // merge repeated (a, b) pairs
-    const unsigned gt = grid_for(total_ub, 256, 65536);
-    k_mark_heads<K><<<gt, 256, 0, s>>>(total_ub, off + n, keys, head);
-    CLEORA_LAUNCH_CHECK();
-    k_mark_row_starts<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, off, head);
-    CLEORA_LAUNCH_CHECK();
-    exclusive_scan(head, total_ub, pos, ws, s);
-    k_compact<K><<<gt, 256, 0, s>>>(total_ub, off + n, keys, head, pos, c->col.as<int32_t>(), esum);
-    CLEORA_LAUNCH_CHECK();
-    k_rowptr<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(n, off, pos, c->rp.as<int64_t>());
-    CLEORA_LAUNCH_CHECK();
-    // D and M values
-    k_rowsum_wave<<<(unsigned)ceil_div(n, 4), 256, 0, s>>>(n, off, MID_CAP, c->rp.as<int64_t>(),
-                                                           esum, c->val.as<float>(),
-                                                           c->deg.as<double>());
-    CLEORA_LAUNCH_CHECK();
-    k_rowsum_block<<<512, 1024, 0, s>>>(big_list, counts + 1, c->rp.as<int64_t>(), esum,
-                                        c->val.as<float>(), c->deg.as<double>());
-    CLEORA_LAUNCH_CHECK();
-    // read back: error word and nnz
-    CLEORA_HIP(hipMemcpyAsync(c->h_small, small, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    CLEORA_HIP(hipMemcpyAsync(c->h_small + 1, c->rp.as<int64_t>() + n, sizeof(int64_t),
-                              hipMemcpyDeviceToHost, s));
-    CLEORA_HIP(hipStreamSynchronize(s));
-    const uint32_t e = (uint32_t)(c->h_small[0] & 0xffffffff);
-    if (e) {
-        throw Error(CLEORA_E_INPUT, (e & ERR_ID) ? "edge id outside [0, n_nodes)"
-                                                 : "edge weight not finite and positive");
-    }
-    c->nnz = c->h_small[1];
+    int b = 1;
+    while (b < 31 && ((int64_t)1 << b) < n) ++b;
+    return b;
 }
 
 }  // namespace
@@ -458,9 +320,96 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const 
 {
     c->has_graph = false;
     c->has_emb = false;
+    const int directed = (flags & CLEORA_DIRECTED) ? 1 : 0;
+    const int64_t total = directed ? m : 2 * m;  // stored entries before merging
+    const int64_t tot1 = std::max<int64_t>(total, 1);
+    const int cb = bits_for(n);
+    const int key_bits = 2 * cb + 1;  // row, column, and the bit of the invalid key
+    const uint64_t invalid_key = (uint64_t)1 << (2 * cb);
+    const uint64_t cmask = ((uint64_t)1 << cb) - 1;
+    const int64_t nblk = ceil_div(tot1, RS_TILE);
+
     c->t_small.ensure(sizeof(int64_t) * 8);
-    if (w) build_typed<uint64_t>(c, n, m, src, dst, w, flags, s);
-    else build_typed<uint32_t>(c, n, m, src, dst, w, flags, s);
+    c->t_keys.ensure(sizeof(uint64_t) * (size_t)tot1);
+    c->t_tmp.ensure(sizeof(uint64_t) * (size_t)tot1);
+    c->t_esum.ensure(sizeof(double) * (size_t)tot1);
+    c->t_head.ensure((size_t)tot1);
+    c->t_cnt.ensure(std::max(sizeof(int32_t) * 256 * (size_t)nblk, sizeof(int32_t) * (size_t)n));
+    c->t_pos.ensure(sizeof(int64_t) * std::max((size_t)tot1 + 1, 256 * (size_t)nblk + 1));
+    c->t_scan.ensure(sizeof(int64_t) *
+                     scan_workspace_elems(std::max<int64_t>(tot1 + 1, 256 * nblk + 1)));
+    // weight payload (kept apart from t_edges, which may hold the input edges)
+    c->t_wts.ensure(w ? 2 * sizeof(float) * (size_t)tot1 : 256);
+    c->rp.ensure(sizeof(int64_t) * ((size_t)n + 1));
+    c->col.ensure(sizeof(int32_t) * (size_t)tot1);
+    c->val.ensure(sizeof(float) * (size_t)tot1);
+    c->deg.ensure(sizeof(double) * (size_t)n);
+
+    int64_t *small = c->t_small.as<int64_t>();
+    uint32_t *err = reinterpret_cast<uint32_t *>(small);                     // [0]
+    unsigned long long *n_valid = reinterpret_cast<unsigned long long *>(small + 1);
+    int32_t *long_count = reinterpret_cast<int32_t *>(small + 2);
+    uint64_t *keys = c->t_keys.as<uint64_t>(), *tmpk = c->t_tmp.as<uint64_t>();
+    float *wa = w ? c->t_wts.as<float>() : nullptr, *wb = w ? wa + tot1 : nullptr;
+    int32_t *count = c->t_cnt.as<int32_t>();
+    int64_t *pos = c->t_pos.as<int64_t>(), *ws = c->t_scan.as<int64_t>();
+    uint8_t *head = c->t_head.as<uint8_t>();
+
+    CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
+    if (m > 0) {
+        k_make_keys<<<grid_for(m, 256, 65536), 256, 0, s>>>(m, n, src, dst, w, directed, cb,
+                                                            invalid_key, keys, wa, err, n_valid);
+        CLEORA_LAUNCH_CHECK();
+    }
+    // stable LSD radix sort of the keys (and weights)
+    if (total > 0) {
+        for (int shift = 0; shift < key_bits; shift += 8) {
+            k_rs_count<<<(unsigned)nblk, RS_THREADS, 0, s>>>(keys, total, shift, nblk, count);
+            CLEORA_LAUNCH_CHECK();
+            exclusive_scan(count, 256 * nblk, pos, ws, s);
+            if (w)
+                k_rs_scatter<true><<<(unsigned)nblk, RS_THREADS, 0, s>>>(keys, wa, total, shift,
+                                                                          nblk, pos, tmpk, wb);
+            else
+                k_rs_scatter<false><<<(unsigned)nblk, RS_THREADS, 0, s>>>(
+                    keys, nullptr, total, shift, nblk, pos, tmpk, nullptr);
+            CLEORA_LAUNCH_CHECK();
+            std::swap(keys, tmpk);
+            std::swap(wa, wb);
+        }
+    }
+    // merge repeated pairs
+    const unsigned gt = grid_for(tot1, 256, 65536);
+    k_mark_heads<<<gt, 256, 0, s>>>(tot1, n_valid, keys, head);
+    CLEORA_LAUNCH_CHECK();
+    exclusive_scan(head, tot1, pos, ws, s);
+    uint64_t *ukeys = tmpk;  // the other key buffer is free now
+    double *esum = c->t_esum.as<double>();
+    k_compact<<<gt, 256, 0, s>>>(tot1, n_valid, keys, wa, head, pos, cmask, ukeys,
+                                 c->col.as<int32_t>(), esum);
+    CLEORA_LAUNCH_CHECK();
+    k_rowptr_search<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(n, pos + tot1, ukeys, cb,
+                                                                c->rp.as<int64_t>());
+    CLEORA_LAUNCH_CHECK();
+    // deg(a) and M values
+    int32_t *long_list = count;  // the digit counts are no longer needed
+    k_rowsum_wave<<<(unsigned)ceil_div(n, 4), 256, 0, s>>>(n, c->rp.as<int64_t>(), esum,
+                                                           c->val.as<float>(), c->deg.as<double>(),
+                                                           long_list, long_count);
+    CLEORA_LAUNCH_CHECK();
+    k_rowsum_block<<<256, 1024, 0, s>>>(long_list, long_count, c->rp.as<int64_t>(), esum,
+                                        c->val.as<float>(), c->deg.as<double>());
+    CLEORA_LAUNCH_CHECK();
+    CLEORA_HIP(hipMemcpyAsync(c->h_small, small, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CLEORA_HIP(hipMemcpyAsync(c->h_small + 1, pos + tot1, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              s));
+    CLEORA_HIP(hipStreamSynchronize(s));
+    const uint32_t e = (uint32_t)(c->h_small[0] & 0xffffffff);
+    if (e) {
+        throw Error(CLEORA_E_INPUT, (e & ERR_ID) ? "edge id outside [0, n_nodes)"
+                                                 : "edge weight not finite and positive");
+    }
+    c->nnz = c->h_small[1];
     c->n = n;
     c->m_in = m;
     c->flags = flags;

@@ -90,7 +90,7 @@ struct cleora_ctx {
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
 
     // build temporaries (grow-only)
-    cleora::DevBuf t_edges, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
+    cleora::DevBuf t_edges, t_wts, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
         t_scan, t_small, multi_desc;
     int64_t *h_small = nullptr;  // pinned host mirror of t_small
 

@@ -191,7 +191,7 @@ void cleora_destroy(cleora_ctx *c)
         (void)hipDeviceSynchronize();
         DevBuf *bufs[] = {&c->rp, &c->col, &c->val, &c->deg, &c->E[0], &c->E[1],
                           &c->split_items, &c->bucket_row, &c->long_rows, &c->chunk_base,
-                          &c->partial, &c->desc, &c->t_edges, &c->t_cnt, &c->t_off, &c->t_keys,
+                          &c->partial, &c->desc, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
                           &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
                           &c->t_scan, &c->t_small, &c->multi_desc};
         for (DevBuf *b : bufs) b->release();
@@ -323,6 +323,20 @@ int cleora_info(cleora_ctx *c, int64_t *n, int64_t *nnz, int32_t *dim, int32_t *
     if (dim) *dim = c->has_emb ? c->dim : 0;
     if (dtype) *dtype = c->dtype;
     if (iteration) *iteration = c->has_emb ? c->iteration : 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_schedule_info(cleora_ctx *c, int32_t *chunk, int64_t *n_split, int64_t *n_long,
+                         int64_t *n_buckets)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
+    if (chunk) *chunk = c->chunk;
+    if (n_split) *n_split = c->n_split;
+    if (n_long) *n_long = c->n_long;
+    if (n_buckets) *n_buckets = c->n_buckets;
     return CLEORA_OK;
     ABI_END
 }
