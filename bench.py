@@ -41,6 +41,63 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def summarize_trace(trace_dir: str, out: str, command: str) -> None:
+    """Per-kernel summary (calls, average and total duration) of a
+    rocprofv3 --kernel-trace --output-format csv run, as a short text file."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    agg = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"]
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            a = agg.setdefault(name, [0, 0.0])
+            a[0] += 1
+            a[1] += dur
+    rows = sorted(agg.items(), key=lambda kv: -kv[1][1])
+    with open(out, "w") as f:
+        f.write(f"# rocprofv3 kernel trace summary\n# command: {command}\n")
+        f.write(f"# kernel source sha256[:16]: {kernel_source_hash()}\n")
+        f.write(f"{'calls':>6} {'avg_ms':>10} {'total_ms':>10}  kernel\n")
+        for name, (n, tot) in rows:
+            f.write(f"{n:6d} {tot / n:10.4f} {tot:10.3f}  {name[:150]}\n")
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
+                  copy_bytes: int) -> None:
+    """HBM-side traffic per launch of the SpMM kernel from two rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
+    what the same counter reads for a plain device copy of copy_bytes."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        rows = [r for fn in f for r in csv.DictReader(open(fn)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    res = {"command": command, "kernel_source_sha256_16": kernel_source_hash()}
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = load(d, counter)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref = max(copies) * 1024.0  # the calibration copy is the largest copy
+        scale = copy_bytes / ref
+        spmm = [float(r["Counter_Value"]) for r in rows if "k_spmm_norm" in r["Kernel_Name"]]
+        res[f"{tag}_kib_per_launch_raw"] = sum(spmm) / len(spmm)
+        res[f"{tag}_copy_kib_raw"] = ref / 1024.0
+        res[f"{tag}_scale"] = scale
+        res[f"{tag}_bytes_per_launch"] = sum(spmm) / len(spmm) * 1024.0 * scale
+        res[f"{tag}_launches"] = len(spmm)
+    res["hbm_bytes_per_launch"] = res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"]
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +116,13 @@ def parse():
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
+        summarize_trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-pmc":
+        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[6:]),
+                      int(sys.argv[5]))
+        return
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "

@@ -55,8 +55,11 @@ struct Variant {
 };
 Variant choose_variant(int dtype, int ld);
 
-void launch_spmm(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
-                 hipStream_t s);
+// One context: the descriptor's fields become kernel arguments.
+void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s);
+// Several contexts: `descs` is a device table with wave_begin prefixes.
+void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
+                       hipStream_t s);
 void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,
                     hipStream_t s);
 // T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and

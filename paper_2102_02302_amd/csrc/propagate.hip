@@ -24,6 +24,17 @@ namespace cleora {
 
 namespace {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Rows of T_t are written once per iteration and read only by the next one:
+// store them non-temporally.
+__device__ __forceinline__ void store_stream(uint4 *p, uint4 x)
+{
+    u32x4 v = {x.x, x.y, x.z, x.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+}
+
+
 // ----------------------------------------------------------------- init
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
@@ -216,12 +227,14 @@ __device__ __forceinline__ void gather_rows(float (&acc)[VPL][EmbT<T>::EPV], int
         }
         uint4 x[U][VPL];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            const uint4 *row = Ein + (int64_t)c[u] * vrow;
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 const int ch = gl + v * LPG;
-                x[u][v] = ch < cpr ? Ein[(int64_t)c[u] * vrow + ch] : make_uint4(0, 0, 0, 0);
+                x[u][v] = ch < cpr ? row[ch] : make_uint4(0, 0, 0, 0);
             }
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -237,12 +250,13 @@ __device__ __forceinline__ void gather_rows(float (&acc)[VPL][EmbT<T>::EPV], int
         if (jj < je) {
             const int32_t c = col[jj];
             const float w = val[jj];
+            const uint4 *row = Ein + (int64_t)c * vrow;
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 const int ch = gl + v * LPG;
                 if (ch < cpr) {
                     float f[EPV];
-                    widen<T>(Ein[(int64_t)c * vrow + ch], f);
+                    widen<T>(row[ch], f);
 #pragma unroll
                     for (int e = 0; e < EPV; ++e) acc[v][e] = fmaf(w, f[e], acc[v][e]);
                 }
@@ -265,38 +279,38 @@ __device__ __forceinline__ void reduce_groups(float (&acc)[VPL][EPV])
     }
 }
 
+// One wave's work item of the fused SpMM + normalise step: either a chunk
+// of a split row (partial sum to `partial`) or a packed group of rows
+// (normalised rows to Eout).
 template <typename T, int G, int VPL, int U>
-__global__ __launch_bounds__(256) void k_spmm_norm(const StepDesc *__restrict__ descs, int n_desc,
-                                                   int cpr)
+__device__ __forceinline__ void spmm_item(
+    int64_t wave, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const float *__restrict__ val, const uint4 *__restrict__ Ein, uint4 *__restrict__ Eout,
+    float *__restrict__ partial, const int2 *__restrict__ split_items,
+    const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
+    int chunk, uint32_t flags, int cpr)
 {
     constexpr int EPV = EmbT<T>::EPV;
     constexpr int LPG = WAVE / G;
     const int lane = threadIdx.x & 63;
     const int grp = G == 1 ? 0 : lane / LPG;
     const int gl = G == 1 ? lane : lane % LPG;
-    // the wave index is uniform: keep it (and every address derived from it)
-    // in scalar registers
-    int64_t wave = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const StepDesc &D = descs[find_desc(descs, n_desc, wave, false)];
-    wave -= D.wave_begin;
-    const int64_t vrow = D.ld / EPV;  // 16-byte vectors per row of T
-    const uint4 *__restrict__ Ein = reinterpret_cast<const uint4 *>(D.Ein);
-    const int64_t *__restrict__ rp = D.rp;
+    const int64_t vrow = ld / EPV;  // 16-byte vectors per row of T
 
     float acc[VPL][EPV];
-    if (wave < D.n_split) {
-        const int2 it = D.split_items[wave];
+    if (wave < n_split) {
+        const int2 it = split_items[wave];
         const int64_t hi = rp[it.x + 1];
-        const int64_t jb = rp[it.x] + (int64_t)it.y * D.chunk;
-        const int64_t je = min(jb + (int64_t)D.chunk, hi);
+        const int64_t jb = rp[it.x] + (int64_t)it.y * chunk;
+        const int64_t je = min(jb + (int64_t)chunk, hi);
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
 #pragma unroll
             for (int e = 0; e < EPV; ++e) acc[v][e] = 0.0f;
-        gather_rows<T, G, VPL, U>(acc, jb, je, D.col, D.val, Ein, vrow, grp, gl, cpr);
+        gather_rows<T, G, VPL, U>(acc, jb, je, col, val, Ein, vrow, grp, gl, cpr);
         reduce_groups<G, VPL, EPV>(acc);
         if (grp == 0) {
-            float4 *prow = reinterpret_cast<float4 *>(D.partial + wave * (int64_t)D.ld);
+            float4 *prow = reinterpret_cast<float4 *>(partial + wave * (int64_t)ld);
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
                 const int ch = gl + v * LPG;
@@ -310,19 +324,18 @@ __global__ __launch_bounds__(256) void k_spmm_norm(const StepDesc *__restrict__ 
         }
         return;
     }
-    const int64_t k = wave - D.n_split;
-    if (k >= D.n_buckets) return;
-    const int32_t r0 = D.bucket_row[k], r1 = D.bucket_row[k + 1];
-    uint4 *__restrict__ Eout = reinterpret_cast<uint4 *>(D.Eout);
+    const int64_t k = wave - n_split;
+    if (k >= n_buckets) return;
+    const int32_t r0 = bucket_row[k], r1 = bucket_row[k + 1];
     for (int32_t r = r0; r < r1; ++r) {
         const int64_t lo = rp[r], hi = rp[r + 1];
-        if (hi - lo > D.chunk) continue;  // split row: chunks + combine
+        if (hi - lo > chunk) continue;  // split row: chunks + combine
 #pragma unroll
         for (int v = 0; v < VPL; ++v)
 #pragma unroll
             for (int e = 0; e < EPV; ++e) acc[v][e] = 0.0f;
         if (hi == lo) {
-            if ((D.flags & CLEORA_EMPTY_KEEP) && grp == 0) {
+            if ((flags & CLEORA_EMPTY_KEEP) && grp == 0) {
 #pragma unroll
                 for (int v = 0; v < VPL; ++v) {
                     const int ch = gl + v * LPG;
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(256) void k_spmm_norm(const StepDesc *__restrict__ 
                 }
             }
         } else {
-            gather_rows<T, G, VPL, U>(acc, lo, hi, D.col, D.val, Ein, vrow, grp, gl, cpr);
+            gather_rows<T, G, VPL, U>(acc, lo, hi, col, val, Ein, vrow, grp, gl, cpr);
         }
         reduce_groups<G, VPL, EPV>(acc);
         float ss = 0.0f;
@@ -348,11 +361,47 @@ __global__ __launch_bounds__(256) void k_spmm_norm(const StepDesc *__restrict__ 
                     float o[EPV];
 #pragma unroll
                     for (int e = 0; e < EPV; ++e) o[e] = acc[v][e] * inv;
-                    Eout[(int64_t)r * vrow + ch] = narrow<T>(o);
+                    // written once, read by the next iteration: keep it out of L2
+                    store_stream(&Eout[(int64_t)r * vrow + ch], narrow<T>(o));
                 }
             }
         }
     }
+}
+
+// The wave index is uniform: readfirstlane keeps it, and every address
+// derived from it, in scalar registers.
+__device__ __forceinline__ int64_t wave_id()
+{
+    return (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// One graph: plain restrict-qualified global pointers, so column/value
+// loads of a wave become scalar loads and gathers global loads.
+template <typename T, int G, int VPL, int U>
+__global__ __launch_bounds__(256) void k_spmm_norm(
+    const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const float *__restrict__ val, const uint4 *__restrict__ Ein, uint4 *__restrict__ Eout,
+    float *__restrict__ partial, const int2 *__restrict__ split_items,
+    const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
+    int chunk, uint32_t flags, int cpr)
+{
+    spmm_item<T, G, VPL, U>(wave_id(), rp, col, val, Ein, Eout, partial, split_items, bucket_row,
+                            n_split, n_buckets, ld, chunk, flags, cpr);
+}
+
+// Several graphs (continuous batching): each wave finds its graph in the
+// descriptor table.
+template <typename T, int G, int VPL, int U>
+__global__ __launch_bounds__(256) void k_spmm_norm_multi(const StepDesc *__restrict__ descs,
+                                                         int n_desc, int cpr)
+{
+    int64_t wave = wave_id();
+    const StepDesc &D = descs[find_desc(descs, n_desc, wave, false)];
+    spmm_item<T, G, VPL, U>(wave - D.wave_begin, D.rp, D.col, D.val,
+                            reinterpret_cast<const uint4 *>(D.Ein),
+                            reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items,
+                            D.bucket_row, D.n_split, D.n_buckets, D.ld, D.chunk, D.flags, cpr);
 }
 
 // Combine the partial sums of a split row in chunk order, normalise, store.
@@ -439,34 +488,43 @@ unsigned grid_for(int64_t items, int threads, int64_t cap = 1 << 20)
 }
 
 template <typename T, int G, int VPL, int U>
-void spmm_launch(const StepDesc *descs, int n_desc, int64_t waves, int cpr, hipStream_t s)
+void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_t waves, int cpr,
+                 hipStream_t s)
 {
     const int64_t blocks = ceil_div(waves, 4);
     if (blocks <= 0) return;
     if (blocks > 0x7fffffffLL) throw Error(CLEORA_E_INVAL, "propagation grid too large");
-    k_spmm_norm<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, cpr);
+    if (host) {
+        const StepDesc &D = *host;
+        k_spmm_norm<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(
+            D.rp, D.col, D.val, reinterpret_cast<const uint4 *>(D.Ein),
+            reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items, D.bucket_row, D.n_split,
+            D.n_buckets, D.ld, D.chunk, D.flags, cpr);
+    } else {
+        k_spmm_norm_multi<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, cpr);
+    }
     CLEORA_LAUNCH_CHECK();
 }
 
 template <typename T>
-void spmm_dispatch(const Variant &v, const StepDesc *descs, int n_desc, int64_t waves,
-                   hipStream_t s)
+void spmm_dispatch(const Variant &v, const StepDesc *host, const StepDesc *descs, int n_desc,
+                   int64_t waves, hipStream_t s)
 {
     if (v.VPL == 1) {
         switch (v.G) {
-        case 1: return spmm_launch<T, 1, 1, 8>(descs, n_desc, waves, v.cpr, s);
-        case 2: return spmm_launch<T, 2, 1, 4>(descs, n_desc, waves, v.cpr, s);
-        case 4: return spmm_launch<T, 4, 1, 2>(descs, n_desc, waves, v.cpr, s);
-        case 8: return spmm_launch<T, 8, 1, 1>(descs, n_desc, waves, v.cpr, s);
-        case 16: return spmm_launch<T, 16, 1, 1>(descs, n_desc, waves, v.cpr, s);
+        case 1: return spmm_launch<T, 1, 1, 8>(host, descs, n_desc, waves, v.cpr, s);
+        case 2: return spmm_launch<T, 2, 1, 4>(host, descs, n_desc, waves, v.cpr, s);
+        case 4: return spmm_launch<T, 4, 1, 2>(host, descs, n_desc, waves, v.cpr, s);
+        case 8: return spmm_launch<T, 8, 1, 1>(host, descs, n_desc, waves, v.cpr, s);
+        case 16: return spmm_launch<T, 16, 1, 1>(host, descs, n_desc, waves, v.cpr, s);
         default: break;
         }
     } else {
         switch (v.VPL) {
-        case 2: return spmm_launch<T, 1, 2, 4>(descs, n_desc, waves, v.cpr, s);
-        case 4: return spmm_launch<T, 1, 4, 2>(descs, n_desc, waves, v.cpr, s);
-        case 8: return spmm_launch<T, 1, 8, 1>(descs, n_desc, waves, v.cpr, s);
-        case 16: return spmm_launch<T, 1, 16, 1>(descs, n_desc, waves, v.cpr, s);
+        case 2: return spmm_launch<T, 1, 2, 4>(host, descs, n_desc, waves, v.cpr, s);
+        case 4: return spmm_launch<T, 1, 4, 2>(host, descs, n_desc, waves, v.cpr, s);
+        case 8: return spmm_launch<T, 1, 8, 1>(host, descs, n_desc, waves, v.cpr, s);
+        case 16: return spmm_launch<T, 1, 16, 1>(host, descs, n_desc, waves, v.cpr, s);
         default: break;
         }
     }
@@ -526,11 +584,18 @@ Variant choose_variant(int dtype, int ld)
     return v;
 }
 
-void launch_spmm(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
-                 hipStream_t s)
+void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s)
 {
-    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, descs, n_desc, total_waves, s);
-    else spmm_dispatch<float>(v, descs, n_desc, total_waves, s);
+    const int64_t waves = one.n_split + one.n_buckets;
+    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, &one, nullptr, 1, waves, s);
+    else spmm_dispatch<float>(v, &one, nullptr, 1, waves, s);
+}
+
+void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
+                       hipStream_t s)
+{
+    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, nullptr, descs, n_desc, total_waves, s);
+    else spmm_dispatch<float>(v, nullptr, descs, n_desc, total_waves, s);
 }
 
 void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,

@@ -95,7 +95,7 @@ void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
             b = take_event(c);
             CLEORA_HIP(hipEventRecord(a, s));
         }
-        cleora::launch_spmm(v, d, 1, c->n_split + c->n_buckets, s);
+        cleora::launch_spmm(v, cleora::host_desc(c, c->cur), s);
         if (c->timing) {
             CLEORA_HIP(hipEventRecord(b, s));
             c->ev_spmm.emplace_back(a, b);
@@ -497,7 +497,7 @@ int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream)
                               hipMemcpyHostToDevice, s));
     const cleora::Variant v = cleora::choose_variant(c0->dtype, c0->ld);
     const StepDesc *d = c0->multi_desc.as<StepDesc>();
-    cleora::launch_spmm(v, d, n, waves, s);
+    cleora::launch_spmm_multi(v, d, n, waves, s);
     if (blocks > 0) cleora::launch_combine(v, d, n, blocks, s);
     for (int32_t i = 0; i < n; ++i) {
         ctxs[i]->cur ^= 1;
