@@ -70,6 +70,11 @@ def _load():
         lib.oracle_step_rows.argtypes = [i64, i64, i32, p, p, p, p, p, ctypes.c_uint]
         lib.oracle_propagate.restype = None
         lib.oracle_propagate.argtypes = [i64, i32, p, p, p, p, p, ctypes.c_int, ctypes.c_uint]
+        lib.oracle_adjacency_rows.restype = ctypes.c_int
+        lib.oracle_adjacency_rows.argtypes = [i64, i64, p, p, p, ctypes.c_int, p, i64, p, p, p,
+                                              i64, ctypes.POINTER(i64)]
+        lib.oracle_t1_rows.restype = None
+        lib.oracle_t1_rows.argtypes = [i64, p, i32, u64, p, p, p, p, ctypes.c_uint]
         lib.oracle_set_threads.restype = None
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_get_threads.restype = ctypes.c_int
@@ -175,6 +180,44 @@ def propagate(adj: Adjacency, mval: np.ndarray, T0: np.ndarray, k: int,
     _load().oracle_propagate(n, d, _ptr(adj.row_ptr), _ptr(adj.col), _ptr(mval), _ptr(T),
                              _ptr(tmp), int(k), flags)
     return T
+
+
+def adjacency_rows(g, rows: np.ndarray) -> Adjacency:
+    """A restricted to the listed rows (any order, no repeats): a CSR whose
+    row i is row rows[i] of the full adjacency."""
+    lib = _load()
+    rows = np.ascontiguousarray(rows, np.int32)
+    in_sample = np.zeros(g.n, np.int64)
+    in_sample[rows] = np.arange(1, rows.size + 1)
+    src = np.ascontiguousarray(g.src, np.int32)
+    dst = np.ascontiguousarray(g.dst, np.int32)
+    w = None if g.w is None else np.ascontiguousarray(g.w, np.float32)
+    # capacity: every edge touching a sampled row, in both directions
+    touch = int(np.count_nonzero(in_sample[src])) + int(np.count_nonzero(in_sample[dst]))
+    cap = max(1, touch)
+    sub_ptr = np.empty(rows.size + 1, np.int64)
+    col = np.empty(cap, np.int32)
+    aval = np.empty(cap, np.float64)
+    nnz = ctypes.c_int64(0)
+    rc = lib.oracle_adjacency_rows(g.n, src.size, _ptr(src), _ptr(dst), _ptr(w),
+                                   int(g.directed), _ptr(in_sample), rows.size, _ptr(sub_ptr),
+                                   _ptr(col), _ptr(aval), cap, ctypes.byref(nnz))
+    if rc == -1:
+        raise ValueError("edge id outside [0, n) or weight not finite and positive")
+    if rc != 0:
+        raise MemoryError(f"oracle_adjacency_rows failed ({rc})")
+    k = nnz.value
+    return Adjacency(rows.size, sub_ptr, col[:k].copy(), aval[:k].copy())
+
+
+def t1_rows(g, rows: np.ndarray, d: int, seed: int, flags: int = 0) -> np.ndarray:
+    """T_1 for the listed rows, computed from the graph and the seed alone."""
+    rows = np.ascontiguousarray(rows, np.int32)
+    sub = adjacency_rows(g, rows)
+    out = np.empty((rows.size, d), np.float64)
+    _load().oracle_t1_rows(rows.size, _ptr(rows), d, seed & (2**64 - 1), _ptr(sub.row_ptr),
+                           _ptr(sub.col), _ptr(sub.aval), _ptr(out), flags)
+    return out
 
 
 def embed(g, d: int, k: int, seed: int, flags: int = 0) -> np.ndarray:

@@ -213,6 +213,116 @@ void oracle_propagate(int64_t n, int32_t d, const int64_t *row_ptr, const int32_
     }
 }
 
+/* ------------------------------------------------ sampled rows, k = 1 */
+
+/* Rows `rows[0..r)` of A only (Section 3.2 definition applied to a subset
+ * of rows): entries of every edge whose source (or, undirected, either end)
+ * is a listed row, merged as in oracle_build_adjacency.  in_sample[a] is
+ * the position of row a in `rows` plus one, 0 if a is not listed (caller
+ * provides it, size n).  Outputs: sub_ptr[r+1], col[cap], aval[cap];
+ * *nnz gets the total.  Returns 0, -1 on invalid input, -2 on no memory,
+ * -3 if cap is too small. */
+int oracle_adjacency_rows(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                          const float *w, int directed, const int64_t *in_sample, int64_t r,
+                          int64_t *sub_ptr, int32_t *col, double *aval, int64_t cap,
+                          int64_t *nnz)
+{
+    int64_t *count = (int64_t *)calloc((size_t)r + 1, sizeof(int64_t));
+    if (!count) return -2;
+    for (int64_t e = 0; e < m; e++) {
+        if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) {
+            free(count);
+            return -1;
+        }
+        if (w && !(isfinite(w[e]) && w[e] > 0.0f)) {
+            free(count);
+            return -1;
+        }
+        if (in_sample[src[e]]) count[in_sample[src[e]] - 1]++;
+        if (!directed && src[e] != dst[e] && in_sample[dst[e]]) count[in_sample[dst[e]] - 1]++;
+    }
+    int64_t *start = (int64_t *)malloc(((size_t)r + 1) * sizeof(int64_t));
+    if (!start) {
+        free(count);
+        return -2;
+    }
+    start[0] = 0;
+    for (int64_t i = 0; i < r; i++) start[i + 1] = start[i] + count[i];
+    int64_t total = start[r];
+    entry_t *ent = (entry_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(entry_t));
+    if (!ent) {
+        free(count); free(start);
+        return -2;
+    }
+    memset(count, 0, ((size_t)r + 1) * sizeof(int64_t));
+    for (int64_t e = 0; e < m; e++) {
+        double we = w ? (double)w[e] : 1.0;
+        int64_t ia = in_sample[src[e]], ib = in_sample[dst[e]];
+        if (ia) {
+            ent[start[ia - 1] + count[ia - 1]].col = dst[e];
+            ent[start[ia - 1] + count[ia - 1]].w = we;
+            count[ia - 1]++;
+        }
+        if (!directed && src[e] != dst[e] && ib) {
+            ent[start[ib - 1] + count[ib - 1]].col = src[e];
+            ent[start[ib - 1] + count[ib - 1]].w = we;
+            count[ib - 1]++;
+        }
+    }
+    int64_t out = 0;
+    sub_ptr[0] = 0;
+    for (int64_t i = 0; i < r; i++) {
+        int64_t lo = start[i], hi = start[i + 1];
+        qsort(ent + lo, (size_t)(hi - lo), sizeof(entry_t), entry_cmp);
+        for (int64_t p = lo; p < hi; p++) {
+            if (p > lo && ent[p].col == ent[p - 1].col) {
+                aval[out - 1] += ent[p].w;
+            } else {
+                if (out >= cap) {
+                    free(count); free(start); free(ent);
+                    return -3;
+                }
+                col[out] = ent[p].col;
+                aval[out] = ent[p].w;
+                out++;
+            }
+        }
+        sub_ptr[i + 1] = out;
+    }
+    *nnz = out;
+    free(count); free(start); free(ent);
+    return 0;
+}
+
+/* T_1 for r sampled rows straight from the seed: with M_ab = e_ab/deg(a)
+ * for the listed rows (sub-CSR from oracle_adjacency_rows),
+ *   T_1[a] = normalise( sum_b M_ab T_0[b] ),  T_0[b][j] = oracle_uniform(seed, b, d, j)
+ * (Algorithm 1, first iteration).  Empty rows give zero rows, or T_0[a]
+ * normalised with ORACLE_EMPTY_KEEP.  out is r x d. */
+void oracle_t1_rows(int64_t r, const int32_t *rows, int32_t d, uint64_t seed,
+                    const int64_t *sub_ptr, const int32_t *col, const double *aval, double *out,
+                    unsigned flags)
+{
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (i = 0; i < r; i++) {
+        double *u = out + i * d;
+        double deg = 0.0;
+        for (int64_t p = sub_ptr[i]; p < sub_ptr[i + 1]; p++) deg += aval[p];
+        for (int32_t j = 0; j < d; j++) u[j] = 0.0;
+        if (sub_ptr[i] == sub_ptr[i + 1] && (flags & ORACLE_EMPTY_KEEP))
+            for (int32_t j = 0; j < d; j++) u[j] = oracle_uniform(seed, rows[i], d, j);
+        for (int64_t p = sub_ptr[i]; p < sub_ptr[i + 1]; p++) {
+            double mab = aval[p] / deg;
+            for (int32_t j = 0; j < d; j++) u[j] += mab * oracle_uniform(seed, col[p], d, j);
+        }
+        double ss = 0.0;
+        for (int32_t j = 0; j < d; j++) ss += u[j] * u[j];
+        double norm = sqrt(ss);
+        for (int32_t j = 0; j < d; j++) u[j] = norm > 0.0 ? u[j] / norm : 0.0;
+    }
+}
+
 /* ------------------------------------------------------------- threads */
 
 void oracle_set_threads(int n)

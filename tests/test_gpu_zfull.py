@@ -1,0 +1,157 @@
+"""GPU parity at the full workload sizes.
+
+* ``chunglu1m`` (the benchmarked workload: N = 1M, 40M stored entries,
+  d = 256 FP32, k = 4) in the launch configuration ``bench.py`` times,
+  compared with the FP64 oracle on every element.
+* ``chunglu10m`` (N = 10M, 400M entries, d = 1024) and ``bipartite6m``
+  (6M nodes, weighted, d = 512 BF16): the first iteration on sampled rows,
+  which the oracle computes one by one from the seed, and properties that
+  hold at any size after all k iterations (unit rows, zero rows, finite
+  values).  BF16 is also compared with the FP32 path on the same GPU.
+"""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+F32_TOL = 1e-5
+BF16_MAXABS = 4e-3
+BF16_MINCOS = 0.9999
+
+
+@pytest.fixture(scope="module")
+def cl():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2102_02302_amd as cl
+    cl.load()
+    return cl
+
+
+def sample_rows(g, n_random, seed):
+    """Uniform random rows plus rows from two degree bands that the GPU
+    splits into chunks (the oracle evaluates T_0 of every neighbour, so the
+    very largest hubs are left to the full-graph test)."""
+    deg = np.bincount(g.src, minlength=g.n)
+    if not g.directed:
+        deg = deg + np.bincount(g.dst, minlength=g.n)
+    rng = np.random.default_rng(seed)
+    picks = [rng.choice(g.n, n_random, replace=False)]
+    for lo, hi in ((200, 2000), (2000, 20000)):
+        band = np.nonzero((deg >= lo) & (deg < hi))[0]
+        if band.size:
+            picks.append(rng.choice(band, min(10, band.size), replace=False))
+    rows = np.unique(np.concatenate(picks)).astype(np.int32)
+    return rows, deg
+
+
+def check_properties(T, deg, tol, chunk=1 << 20):
+    """Rows with out-edges are unit vectors, rows without are zero."""
+    import torch
+    for r0 in range(0, T.shape[0], chunk):
+        nrm = torch.linalg.vector_norm(T[r0:r0 + chunk].float(), dim=1).cpu().numpy()
+        d = deg[r0:r0 + chunk]
+        assert np.all(np.isfinite(nrm))
+        if (d > 0).any():
+            assert np.abs(nrm[d > 0] - 1).max() <= tol, np.abs(nrm[d > 0] - 1).max()
+        assert np.all(nrm[d == 0] == 0)
+
+
+def compare_gpu(a, b, deg, chunk=1 << 20):
+    """max |a - b| and the minimum row cosine over rows with out-edges."""
+    import torch
+    dmax, cmin = 0.0, 1.0
+    for r0 in range(0, a.shape[0], chunk):
+        x, y = a[r0:r0 + chunk].float(), b[r0:r0 + chunk].float()
+        dmax = max(dmax, (x - y).abs().max().item())
+        m = torch.as_tensor(deg[r0:r0 + chunk] > 0, device=x.device)
+        if m.any():
+            cmin = min(cmin, torch.nn.functional.cosine_similarity(x[m], y[m], dim=1).min().item())
+    return dmax, cmin
+
+
+def rowwise_report(got, want):
+    err = float(np.abs(got - want).max())
+    nz = np.linalg.norm(want, axis=1) > 0
+    cos = (got[nz] * want[nz]).sum(1) / (np.linalg.norm(got[nz], axis=1) *
+                                         np.linalg.norm(want[nz], axis=1))
+    return err, float(cos.min()) if cos.size else 1.0
+
+
+@pytest.mark.timeout(900)
+def test_chunglu1m_full_parity(cl):
+    g, dim, k, dtype = gen.workload("chunglu1m")
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g).init(dim, dtype, 2102).propagate(k)
+        got = ctx.embedding().cpu().numpy()
+    want = oracle.embed(g, dim, k, 2102)
+    err = np.abs(got.astype(np.float64) - want).max()
+    print(f"chunglu1m FP32 k={k}: max-abs {err:.3e} over {got.size} values")
+    assert err <= F32_TOL
+
+
+@pytest.mark.timeout(900)
+def test_bipartite6m_sampled(cl):
+    import torch
+    g, dim, k, dtype = gen.workload("bipartite6m")
+    rows, deg = sample_rows(g, 2000, 1)
+    want1 = oracle.t1_rows(g, rows, dim, 7)
+    idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g).init(dim, "f32", 7).propagate(1)
+        f32_1 = ctx.embedding()[idx].cpu().numpy().astype(np.float64)
+        torch.cuda.empty_cache()
+        ctx.propagate(k - 1)
+        f32_k = ctx.embedding()
+        check_properties(f32_k, deg, 1e-5)
+        ctx.init(dim, "bf16", 7).propagate(1)
+        bf_1 = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
+        torch.cuda.empty_cache()
+        ctx.propagate(k - 1)
+        bf_k = ctx.embedding("f32")
+        check_properties(bf_k, deg, 1e-2)
+        d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
+    err32 = np.abs(f32_1 - want1).max()
+    err16, cos16 = rowwise_report(bf_1, want1)
+    print(f"bipartite6m k=1 sampled {rows.size} rows: FP32 max-abs {err32:.3e}; "
+          f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}; k={k} BF16 vs FP32 (GPU, all rows): "
+          f"max-abs {d_all:.3e} min-cos {cos_all:.7f}")
+    assert err32 <= F32_TOL
+    assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
+    assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS
+
+
+@pytest.mark.timeout(1200)
+def test_chunglu10m_sampled(cl):
+    import torch
+    g, dim, k, _ = gen.workload("chunglu10m")
+    rows, deg = sample_rows(g, 1000, 2)
+    want1 = oracle.t1_rows(g, rows, dim, 9)
+    idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g).init(dim, "f32", 9).propagate(1)
+        f32_1 = ctx.embedding()[idx].cpu().numpy().astype(np.float64)
+        torch.cuda.empty_cache()
+        ctx.propagate(k - 1)
+        f32_k = ctx.embedding()
+        check_properties(f32_k, deg, 1e-5)
+        ctx.init(dim, "bf16", 9).propagate(1)
+        bf_1 = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
+        torch.cuda.empty_cache()
+        ctx.propagate(k - 1)
+        bf_k = ctx.embedding("f32")
+        check_properties(bf_k, deg, 1e-2)
+        d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
+        del f32_k, bf_k
+    err32 = np.abs(f32_1 - want1).max()
+    err16, cos16 = rowwise_report(bf_1, want1)
+    print(f"chunglu10m k=1 sampled {rows.size} rows: FP32 max-abs {err32:.3e}; "
+          f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}; k={k} BF16 vs FP32 (GPU, all rows): "
+          f"max-abs {d_all:.3e} min-cos {cos_all:.7f}")
+    assert err32 <= F32_TOL
+    assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
+    assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS

@@ -389,3 +389,31 @@ def test_collapse_bipartite_two_vectors():
     assert np.abs(T[0::2] - T[0]).max() < 1e-12
     assert np.abs(T[1::2] - T[1]).max() < 1e-12
     assert np.abs(T[0] - T[1]).max() > 1e-3
+
+
+# ------------------------------------------------------- sampled rows
+
+def test_sampled_rows_match_dense_first_step():
+    # T_1 for a subset of rows from the seed alone equals row-normalised
+    # A T_0 of the dense brute-force build (Section 3.2, Algorithm 1, k = 1).
+    g = gen.random_graph(120, 700, seed=31, directed=True, weighted=True, loops=True,
+                         multi=True)
+    rows = np.array([5, 0, 119, 37, 64, 2], np.int32)
+    T0 = oracle.init(77, g.n, 12)
+    A = dense_adjacency(g.n, g.src, g.dst, g.w, True)
+    want = normalise_rows(np.matmul(A, T0))[rows]
+    got = oracle.t1_rows(g, rows, 12, 77)
+    assert np.allclose(got, want, atol=1e-14)
+    sub = oracle.adjacency_rows(g, rows)
+    for i, a in enumerate(rows):
+        cols = sub.col[sub.row_ptr[i]:sub.row_ptr[i + 1]]
+        assert np.array_equal(cols, np.nonzero(A[a])[0])
+        assert np.allclose(sub.aval[sub.row_ptr[i]:sub.row_ptr[i + 1]], A[a, cols], rtol=1e-15)
+
+
+def test_sampled_rows_undirected_and_empty_keep():
+    g = gen.random_graph(200, 150, seed=32, loops=True)
+    rows = np.arange(0, 200, 7, dtype=np.int32)
+    for flags in (0, oracle.EMPTY_KEEP):
+        full = oracle.embed(g, 9, 1, 5, flags)
+        assert np.allclose(oracle.t1_rows(g, rows, 9, 5, flags), full[rows], atol=1e-15)
