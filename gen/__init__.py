@@ -14,4 +14,4 @@ from .graphs import (  # noqa: F401
     workload,
     WORKLOADS,
 )
-from .trace import Request, served_trace  # noqa: F401
+from .trace import Request, materialize, served_trace  # noqa: F401

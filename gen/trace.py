@@ -40,3 +40,17 @@ def served_trace(n_requests: int, rate_per_s: float, seed: int = BASE_SEED + 4,
         c = float(rng.uniform(deg_lo, deg_hi))
         out.append(Request(i, float(arrivals[i]), n, c, seed * 1_000_003 + i))
     return out
+
+
+def _make(req: Request) -> Graph:
+    return req.graph()
+
+
+def materialize(requests: List[Request], workers: int = 0) -> List[Graph]:
+    """Generate every request's graph (in worker processes when workers > 1)."""
+    if workers <= 1 or len(requests) < 8:
+        return [r.graph() for r in requests]
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        return pool.map(_make, requests, chunksize=max(1, len(requests) // (4 * workers)))

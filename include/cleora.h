@@ -128,9 +128,9 @@ int cleora_get_csr(cleora_ctx *ctx, int64_t *row_ptr, int32_t *col, float *val, 
 int cleora_info(cleora_ctx *ctx, int64_t *n_nodes, int64_t *nnz, int32_t *dim, int32_t *dtype,
                 int32_t *iteration);
 
-/* Propagation schedule planned by the last cleora_init: entries per work
- * item, number of split chunks, rows split into chunks (finished by the
- * combine step), packed work items.  Any pointer may be NULL.
+/* Propagation schedule planned by the last cleora_init: split size, number
+ * of split pieces, rows split into pieces (finished by the combine step),
+ * packed work items.  Any pointer may be NULL.
  * Errors: E_STATE (no embedding). */
 int cleora_schedule_info(cleora_ctx *ctx, int32_t *chunk, int64_t *n_split_chunks,
                          int64_t *n_split_rows, int64_t *n_packed_items);
@@ -138,10 +138,13 @@ int cleora_schedule_info(cleora_ctx *ctx, int32_t *chunk, int64_t *n_split_chunk
 /* Wait for the stream.  Errors: E_DEVICE. */
 int cleora_sync(cleora_ctx *ctx, void *stream);
 
-/* Per-context tuning: nnz per work item for the SpMM (the unit of load
- * balance; rows longer than this are split and their partial sums combined
- * in a fixed order).  0 restores the default.  Takes effect at the next
- * cleora_init.  Errors: E_INVAL (chunk < 0 or > 2^20). */
+/* Per-context tuning: split size of the SpMM -- rows with more entries are
+ * split into pieces of this many entries whose partial sums are added in a
+ * fixed order (the packing of shorter rows into work items adapts to the
+ * graph by itself).  It fixes the float32 summation order of long rows, so
+ * contexts that must agree bit for bit must use the same value.  0
+ * restores the default (256).  Takes effect at the next cleora_init.
+ * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 
 /* Kernel timing for measurement: when on, the library records HIP events

@@ -1,6 +1,8 @@
 // Internal declarations shared by the translation units of the library.
 #pragma once
 
+#include <map>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -88,7 +90,7 @@ struct cleora_ctx {
     cleora::DevBuf E[2];
 
     // schedule
-    int32_t chunk_req = 0, chunk = 0;
+    int32_t chunk_req = 0, chunk = 0, pack = 0;
     int64_t n_split = 0, n_buckets = 0, n_long = 0;
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
 
@@ -96,6 +98,10 @@ struct cleora_ctx {
     cleora::DevBuf t_edges, t_wts, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
         t_scan, t_small, multi_desc;
     int64_t *h_small = nullptr;  // pinned host mirror of t_small
+
+    // captured k-iteration graphs, keyed by (k, starting parity)
+    std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
+    hipStream_t cap_stream = nullptr;
 
     // timing
     bool timing = false;

@@ -1,14 +1,16 @@
 // The propagation hot path (Algorithm 1 of the paper): T_t = M . T_{t-1}
 // followed by an L2 normalisation of every row, as one fused kernel.
 //
-// Work decomposition.  Rows are packed into items of about `chunk` units of
-// work (one unit per stored entry, one per row for its write): an item is
-// the set of rows whose position rp[r] + r falls into one chunk-sized
-// bucket.  A row with more than `chunk` entries is split into chunks aligned
-// to its own start; every chunk writes a float32 partial sum and a combine
-// kernel adds a row's partials in chunk order, normalises and stores.  Each
-// row's summation order therefore depends only on the row (its entries, its
-// length and `chunk`), never on where it sits in the graph or in a batch.
+// Work decomposition.  A row with more than `chunk` entries (the split size)
+// is split into chunks aligned to its own start; every chunk writes a
+// float32 partial sum and a combine kernel adds a row's partials in chunk
+// order, normalises and stores.  The other rows are packed into items of
+// about `pack` units of work (one unit per stored entry, one per row for its
+// write): an item is the set of rows whose position rp[r] + r falls into one
+// pack-sized bucket.  The packing adapts to the graph's size; the split size
+// does not.  Each row's summation order therefore depends only on the row
+// (its entries, its length and `chunk`), never on where it sits in the graph
+// or in a batch.
 //
 // Inner loop.  A wave (64 lanes) owns a row.  The row of T_{t-1} of each
 // neighbour is gathered with 16-byte loads along d (d contiguous, coalesced);
@@ -631,7 +633,11 @@ void launch_widen_bf16(const void *src, int64_t n, int32_t dim, int32_t ld_src, 
 void plan_schedule(cleora_ctx *c, hipStream_t s)
 {
     const int64_t n = c->n;
-    const int32_t C = c->chunk;
+    const int32_t C = c->chunk;  // split size: rows longer than this are split
+    // packing size: enough items to keep every SIMD busy several times over
+    // (no effect on results: a packed row is summed the same way in any item)
+    c->pack = (int32_t)std::min<int64_t>(C, std::max<int64_t>(16, (c->nnz + n) / 32768));
+    const int32_t P = c->pack;
     c->t_cnt.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     c->t_head.ensure((size_t)std::max<int64_t>(n, 1));
     c->chunk_base.ensure(sizeof(int64_t) * ((size_t)n + 1));
@@ -652,7 +658,7 @@ void plan_schedule(cleora_ctx *c, hipStream_t s)
     CLEORA_HIP(hipStreamSynchronize(s));
     c->n_split = c->h_small[2];
     c->n_long = c->h_small[3];
-    c->n_buckets = (c->nnz + n) / C + 1;
+    c->n_buckets = (c->nnz + n) / P + 1;
     c->split_items.ensure(sizeof(int2) * (size_t)std::max<int64_t>(c->n_split, 1));
     c->long_rows.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(c->n_long, 1));
     c->bucket_row.ensure(sizeof(int32_t) * ((size_t)c->n_buckets + 1));
@@ -661,7 +667,7 @@ void plan_schedule(cleora_ctx *c, hipStream_t s)
                                                          c->long_rows.as<int32_t>());
     CLEORA_LAUNCH_CHECK();
     k_buckets<<<grid_for(c->n_buckets + 1, 256, 65536), 256, 0, s>>>(
-        n, rp, C, c->n_buckets, c->bucket_row.as<int32_t>());
+        n, rp, P, c->n_buckets, c->bucket_row.as<int32_t>());
     CLEORA_LAUNCH_CHECK();
 }
 

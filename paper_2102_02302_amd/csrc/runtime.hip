@@ -2,6 +2,7 @@
 // Every entry point catches everything and returns a CLEORA_* status.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -51,14 +52,12 @@ int32_t padded_ld(int32_t dim, int dtype)
     return (dim + epv - 1) / epv * epv;
 }
 
-// Entries per work item: about 512 KiB of gathered rows per item, within
-// [64, 2048] entries.
-int32_t default_chunk(int32_t ld, int dtype)
-{
-    const int64_t row_bytes = (int64_t)ld * elem_size(dtype);
-    const int64_t c = (512 * 1024) / std::max<int64_t>(row_bytes, 1);
-    return (int32_t)std::min<int64_t>(2048, std::max<int64_t>(64, c));
-}
+// Split size: rows with more entries are split into pieces of this many
+// entries (and recombined in order).  Fixed, so that a graph is summed the
+// same way alone and in any batch; small enough that one piece is a short
+// latency chain for small graphs, large enough that the float32 partial
+// rows it writes (d*4 bytes per piece) stay under 1% of the gathered bytes.
+constexpr int32_t DEFAULT_SPLIT = 256;
 
 void check_dim(int32_t dim, int32_t dtype)
 {
@@ -84,18 +83,19 @@ hipEvent_t take_event(cleora_ctx *c)
     return e;
 }
 
-void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
+// Queue k iterations starting from buffer parity `cur` (no state change).
+void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
 {
     const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
     for (int32_t t = 0; t < k; ++t) {
-        const StepDesc *d = c->desc.as<StepDesc>() + c->cur;
+        const StepDesc d = cleora::host_desc(c, cur);
         hipEvent_t a = nullptr, b = nullptr;
         if (c->timing) {
             a = take_event(c);
             b = take_event(c);
             CLEORA_HIP(hipEventRecord(a, s));
         }
-        cleora::launch_spmm(v, cleora::host_desc(c, c->cur), s);
+        cleora::launch_spmm(v, d, s);
         if (c->timing) {
             CLEORA_HIP(hipEventRecord(b, s));
             c->ev_spmm.emplace_back(a, b);
@@ -106,24 +106,65 @@ void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
                 b = take_event(c);
                 CLEORA_HIP(hipEventRecord(a, s));
             }
-            cleora::launch_combine(v, d, 1, c->n_long, s);
+            cleora::launch_combine(v, c->desc.as<StepDesc>() + cur, 1, c->n_long, s);
             if (c->timing) {
                 CLEORA_HIP(hipEventRecord(b, s));
                 c->ev_comb.emplace_back(a, b);
             }
         }
-        c->cur ^= 1;
-        c->iteration++;
+        cur ^= 1;
     }
+}
+
+void drop_graphs(cleora_ctx *c)
+{
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+// k >= 2 iterations without timing run as one captured graph (cached per
+// k and starting parity): the 2k launches cost one graph launch.
+void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
+{
+    if (k <= 0) return;
+    if (k >= 2 && !c->timing) {
+        const auto key = std::make_pair(k, c->cur);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (!c->cap_stream)
+                CLEORA_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            CLEORA_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_steps(c, k, c->cur, c->cap_stream);
+            } catch (...) {
+                (void)hipStreamEndCapture(c->cap_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            CLEORA_HIP(hipStreamEndCapture(c->cap_stream, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            CLEORA_HIP(e);
+            it = c->graphs.emplace(key, ex).first;
+        }
+        CLEORA_HIP(hipGraphLaunch(it->second, s));
+    } else {
+        enqueue_steps(c, k, c->cur, s);
+    }
+    c->cur ^= (k & 1);
+    c->iteration += k;
 }
 
 void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
 {
+    drop_graphs(c);
     c->has_emb = false;
     c->dim = dim;
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
-    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_chunk(c->ld, dtype);
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
     const size_t ebytes = (size_t)c->n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
@@ -194,6 +235,8 @@ void cleora_destroy(cleora_ctx *c)
                           &c->partial, &c->desc, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
                           &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
                           &c->t_scan, &c->t_small, &c->multi_desc};
+        drop_graphs(c);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         for (DevBuf *b : bufs) b->release();
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->h_small) (void)hipHostFree(c->h_small);
@@ -207,15 +250,16 @@ size_t cleora_footprint_bytes(int64_t n, int64_t m, uint32_t flags, int32_t dim,
     if (n < 1 || m < 0 || dim < 1 || (dtype != CLEORA_F32 && dtype != CLEORA_BF16)) return 0;
     const double t = (flags & CLEORA_DIRECTED) ? (double)m : 2.0 * (double)m;
     const int32_t ld = padded_ld(dim, dtype);
-    const int32_t C = default_chunk(ld, dtype);
     const double N = (double)n;
+    const double S = DEFAULT_SPLIT, P = 16;  // split size; smallest packing size
     double b = 0;
     b += 8 * N + 8 * (N + 1) + 8 * t + 8 * t + t + 8 * (t + 1) + 8 * t + 8 * N;  // build
+    b += 8 * t;                                                                // weights
     b += 8 * 16.0 * ceil(std::max(t, N) / 4096.0);                             // scan
     b += 8 * (N + 1) + 4 * t + 4 * t + 8 * N;                                  // CSR + D
     b += 2.0 * N * ld * elem_size(dtype);                                      // T ping-pong
-    const double split = 2.0 * t / C + 1;
-    b += 8 * (N + 1) + split * (4.0 * ld + 8) + 4 * ((t + N) / C + 2) + 4 * N;  // schedule
+    const double split = 2.0 * t / S + 1;
+    b += 8 * (N + 1) + split * (4.0 * ld + 8) + 4 * ((t + N) / P + 2) + 4 * N;  // schedule
     b += 1 << 20;                                                               // slack
     return (size_t)b;
 }
@@ -229,6 +273,7 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
     if (m > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst is NULL");
     if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
     DeviceGuard g(c->device);
+    drop_graphs(c);
     cleora::build_graph(c, n, m, src, dst, w, flags, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
@@ -427,6 +472,7 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
     check_graph_sizes(N, M);
     DeviceGuard dg(c->device);
     hipStream_t s = cleora::as_stream(stream);
+    drop_graphs(c);
     // concatenated edge list with node offsets, then the ordinary build
     const size_t ebytes = ((size_t)std::max<int64_t>(M, 1) * (any_w ? 12 : 8) + 255) / 256 * 256;
     c->t_edges.ensure(ebytes + sizeof(int64_t) * (row0.size() + seeds.size()) + 64);

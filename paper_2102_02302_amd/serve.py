@@ -1,0 +1,264 @@
+"""Served form: continuous batching of independent embedding requests.
+
+Each request is a whole graph to embed (T_k of Algorithm 1 for its own
+graph and seed).  The server
+
+* admits waiting requests in arrival order while a slot (a library context)
+  is free and the HBM footprint of everything admitted stays within a
+  budget (``cleora_footprint_bytes``);
+* builds an admitted request's CSR and T_0 on a side stream, in a builder
+  thread, while the running requests keep stepping;
+* advances every running request by one iteration per step, all of them in
+  the same kernel launches (``cleora_step_multi``), whatever iteration each
+  is at: a request joins at the next iteration boundary after its build and
+  leaves as soon as it has done its k iterations, freeing its slot and its
+  share of the budget;
+* records latency = completion - arrival per request.
+
+The scheduling policy (``Scheduler``) is plain Python and is tested on the
+CPU with a simulated engine; ``GpuEngine`` is the MI355X implementation.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import queue
+import threading
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+
+@dataclasses.dataclass
+class Job:
+    index: int
+    arrival_s: float
+    n: int
+    m: int
+    seed: int
+    payload: object = None          # host-side graph (src, dst, w, directed)
+    footprint: int = 0
+    admitted_s: float = -1.0
+    ready_s: float = -1.0
+    done_s: float = -1.0
+    iteration: int = 0
+    slot: int = -1
+    result: object = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+class Scheduler:
+    """Admission and iteration-level batching, independent of the device.
+
+    ``engine`` provides: footprint(job) -> bytes; start_build(job, slot)
+    (asynchronous); poll_ready() -> list of jobs whose build finished;
+    step(jobs) (one iteration each, synchronous); finish(job) (collect the
+    result, release device work); idle_wait(seconds)."""
+
+    def __init__(self, engine, k: int, max_slots: int, budget_bytes: int,
+                 clock: Callable[[], float] = time.perf_counter):
+        self.engine = engine
+        self.k = k
+        self.max_slots = max_slots
+        self.budget = budget_bytes
+        self.clock = clock
+        self.used = 0
+        self.peak_used = 0
+        self.max_active = 0
+        self.steps = 0
+        self.step_sizes: List[int] = []
+
+    def run(self, jobs: Sequence[Job]) -> List[Job]:
+        jobs = sorted(jobs, key=lambda j: (j.arrival_s, j.index))
+        for j in jobs:
+            j.footprint = int(self.engine.footprint(j))
+            if j.footprint > self.budget:
+                raise ValueError(f"request {j.index} needs {j.footprint} bytes, "
+                                 f"more than the whole budget {self.budget}")
+        free_slots = collections.deque(range(self.max_slots))
+        pending: collections.deque = collections.deque()
+        building: Dict[int, Job] = {}
+        active: List[Job] = []
+        done: List[Job] = []
+        nxt = 0
+        t0 = self.clock()
+        while len(done) < len(jobs):
+            now = self.clock() - t0
+            while nxt < len(jobs) and jobs[nxt].arrival_s <= now:
+                pending.append(jobs[nxt])
+                nxt += 1
+            # admission: arrival order, a free slot, and the budget
+            while pending and free_slots and self.used + pending[0].footprint <= self.budget:
+                j = pending.popleft()
+                j.slot = free_slots.popleft()
+                j.admitted_s = self.clock() - t0
+                self.used += j.footprint
+                self.peak_used = max(self.peak_used, self.used)
+                building[j.index] = j
+                self.engine.start_build(j, j.slot)
+            for j in self.engine.poll_ready():
+                building.pop(j.index)
+                j.ready_s = self.clock() - t0
+                if self.k == 0:
+                    self._retire(j, t0, free_slots, done)
+                else:
+                    active.append(j)
+            if active:
+                self.max_active = max(self.max_active, len(active))
+                self.engine.step(active)
+                self.steps += 1
+                self.step_sizes.append(len(active))
+                still = []
+                for j in active:
+                    j.iteration += 1
+                    if j.iteration >= self.k:
+                        self._retire(j, t0, free_slots, done)
+                    else:
+                        still.append(j)
+                active = still
+            else:
+                wait = 0.0005
+                if nxt < len(jobs) and not building and not pending:
+                    wait = max(0.0, min(0.01, jobs[nxt].arrival_s - (self.clock() - t0)))
+                self.engine.idle_wait(wait)
+        return done
+
+    def _retire(self, j: Job, t0: float, free_slots, done: List[Job]) -> None:
+        self.engine.finish(j)
+        j.done_s = self.clock() - t0
+        self.used -= j.footprint
+        free_slots.append(j.slot)
+        done.append(j)
+
+
+class GpuEngine:
+    """Requests on one MI355X: one library context per slot (reused, so its
+    device buffers are reused), builds on a side stream in a worker thread,
+    steps with ``step_multi`` on the main stream."""
+
+    def __init__(self, dim: int, dtype: str, max_slots: int, device: int = 0,
+                 keep_results: bool = False, builders: int = 4):
+        import torch
+
+        from . import Context, footprint_bytes
+        self.torch = torch
+        self.dim, self.dtype = dim, dtype
+        self.keep_results = keep_results
+        self._footprint = footprint_bytes
+        self.ctxs = [Context(device) for _ in range(max_slots)]
+        self.main = torch.cuda.Stream(device=device)
+        self._todo: queue.Queue = queue.Queue()
+        self._ready: queue.Queue = queue.Queue()
+        self._err: Optional[BaseException] = None
+        # several builders, each with its own stream, so that the host-side
+        # latency of one build (launches, two synchronisations) overlaps others
+        self._workers = []
+        for _ in range(max(1, builders)):
+            t = threading.Thread(target=self._build_loop,
+                                 args=(torch.cuda.Stream(device=device),), daemon=True)
+            t.start()
+            self._workers.append(t)
+
+    def footprint(self, job: Job) -> int:
+        g = job.payload
+        return self._footprint(job.n, job.m, self.dim, self.dtype, directed=g.directed)
+
+    def start_build(self, job: Job, slot: int) -> None:
+        self._todo.put(job)
+
+    def _build_loop(self, side) -> None:
+        torch = self.torch
+        while True:
+            job = self._todo.get()
+            if job is None:
+                return
+            try:
+                ctx = self.ctxs[job.slot]
+                g = job.payload
+                with torch.cuda.stream(side):
+                    ctx.build_csr(g.n, g.src, g.dst, g.w, directed=g.directed, stream=side)
+                    ctx.init(self.dim, self.dtype, job.seed, stream=side)
+                    ctx.sync(side)
+                self._ready.put(job)
+            except BaseException as e:  # surfaced by poll_ready
+                self._err = e
+                self._ready.put(None)
+
+    def poll_ready(self) -> List[Job]:
+        out = []
+        while True:
+            try:
+                j = self._ready.get_nowait()
+            except queue.Empty:
+                break
+            if j is None:
+                raise RuntimeError("request build failed") from self._err
+            out.append(j)
+        return out
+
+    def step(self, jobs: List[Job]) -> None:
+        from . import step_multi
+        step_multi([self.ctxs[j.slot] for j in jobs], stream=self.main)
+
+    def finish(self, job: Job) -> None:
+        ctx = self.ctxs[job.slot]
+        with self.torch.cuda.stream(self.main):
+            emb = ctx.embedding(stream=self.main)
+            host = emb.to("cpu", non_blocking=False)
+        job.result = host if self.keep_results else None
+
+    def idle_wait(self, seconds: float) -> None:
+        if seconds > 0:
+            time.sleep(seconds)
+
+    def close(self) -> None:
+        for _ in self._workers:
+            self._todo.put(None)
+        for t in self._workers:
+            t.join(timeout=10)
+        for c in self.ctxs:
+            c.close()
+
+
+def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", device: int = 0,
+                  keep_results: bool = False,
+                  clock: Callable[[], float] = time.perf_counter) -> List[Job]:
+    """Baseline: the same arrivals served one request after another by a
+    single context with the plain path (build, init, k iterations, copy)."""
+    import torch
+
+    from . import Context
+    jobs = sorted(jobs, key=lambda j: (j.arrival_s, j.index))
+    out = []
+    with Context(device) as ctx:
+        t0 = clock()
+        for j in jobs:
+            wait = j.arrival_s - (clock() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            j.admitted_s = clock() - t0
+            g = j.payload
+            ctx.build_csr(g.n, g.src, g.dst, g.w, directed=g.directed)
+            ctx.init(dim, dtype, j.seed)
+            ctx.propagate(k)
+            host = ctx.embedding().cpu()
+            j.result = host if keep_results else None
+            j.done_s = clock() - t0
+            out.append(j)
+        torch.cuda.synchronize()
+    return out
+
+
+def latency_stats(done: Sequence[Job], k: int, dim: int, nnz_of: Callable[[Job], int]) -> dict:
+    import numpy as np
+    lat = np.array([j.latency_s for j in done]) * 1e3
+    span = max(j.done_s for j in done) - min(j.arrival_s for j in done)
+    edge_dims = sum(nnz_of(j) for j in done) * float(k) * dim
+    return {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
+            "req_per_s": round(len(done) / span, 2),
+            "gedge_dims_per_s": round(edge_dims / span / 1e9, 3), "span_s": round(span, 3)}

@@ -274,3 +274,21 @@ def test_empty_graph_and_tiny(cl):
     assert np.abs(T - oracle_embed(g, 8, 2, 1, empty_keep=True)).max() <= F32_TOL
     g1 = gen.Graph(1, np.zeros(1, np.int32), np.zeros(1, np.int32), None, False)  # one loop
     assert np.abs(gpu_embed(cl, g1, 3, 3, seed=2) - oracle_embed(g1, 3, 3, 2)).max() <= F32_TOL
+
+
+def test_graph_replays_match_eager(cl):
+    # k >= 2 runs as a captured graph: replay it several times, with eager
+    # single steps in between, and compare every result with all-eager steps
+    g = gen.chung_lu(30_000, 200_000, 2.1, 40)
+    with cl.Context(0) as a, cl.Context(0) as b:
+        a.set_chunk(32)
+        b.set_chunk(32)
+        a.build_graph(g).init(96, "f32", 3)
+        b.build_graph(g).init(96, "f32", 3)
+        for rep in range(4):
+            a.propagate(2)
+            a.propagate(1)
+            for _ in range(3):
+                b.propagate(1)
+            assert np.array_equal(a.embedding().cpu().numpy(), b.embedding().cpu().numpy()), rep
+        assert a.info()["iteration"] == 12
