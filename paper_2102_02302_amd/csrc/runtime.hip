@@ -53,11 +53,17 @@ int32_t padded_ld(int32_t dim, int dtype)
 }
 
 // Split size: rows with more entries are split into pieces of this many
-// entries (and recombined in order).  Fixed, so that a graph is summed the
-// same way alone and in any batch; small enough that one piece is a short
-// latency chain for small graphs, large enough that the float32 partial
-// rows it writes (d*4 bytes per piece) stay under 1% of the gathered bytes.
+// entries (and recombined in order).  A function of the row layout only, so
+// that a graph is summed the same way alone and in any batch; small enough
+// that one piece is a short latency chain for small graphs, large enough
+// that the float32 partial rows it writes (d*4 bytes per piece) stay under
+// 1% of the gathered bytes.  512 for rows of 1 KiB or more (measured best on
+// the 1M-node power-law graph at d = 256), 256 below.
 constexpr int32_t DEFAULT_SPLIT = 256;
+int32_t default_split(int32_t ld, int dtype)
+{
+    return (int64_t)ld * elem_size(dtype) >= 1024 ? 512 : DEFAULT_SPLIT;
+}
 
 void check_dim(int32_t dim, int32_t dtype)
 {
@@ -164,7 +170,7 @@ void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
     c->dim = dim;
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
-    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_split(c->ld, dtype);
     const size_t ebytes = (size_t)c->n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);

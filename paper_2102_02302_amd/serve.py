@@ -22,6 +22,7 @@ CPU with a simulated engine; ``GpuEngine`` is the MI355X implementation.
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import queue
 import threading
@@ -55,8 +56,9 @@ class Scheduler:
 
     ``engine`` provides: footprint(job) -> bytes; start_build(job, slot)
     (asynchronous); poll_ready() -> list of jobs whose build finished;
-    step(jobs) (one iteration each, synchronous); finish(job) (collect the
-    result, release device work); idle_wait(seconds)."""
+    step(jobs) (one iteration each, synchronous); start_finish(job)
+    (asynchronous copy of the result); poll_finished() -> list of jobs whose
+    result is out; idle_wait(seconds)."""
 
     def __init__(self, engine, k: int, max_slots: int, budget_bytes: int,
                  clock: Callable[[], float] = time.perf_counter):
@@ -81,6 +83,7 @@ class Scheduler:
         free_slots = collections.deque(range(self.max_slots))
         pending: collections.deque = collections.deque()
         building: Dict[int, Job] = {}
+        retiring: Dict[int, Job] = {}
         active: List[Job] = []
         done: List[Job] = []
         nxt = 0
@@ -99,11 +102,18 @@ class Scheduler:
                 self.peak_used = max(self.peak_used, self.used)
                 building[j.index] = j
                 self.engine.start_build(j, j.slot)
+            for j in self.engine.poll_finished():
+                retiring.pop(j.index)
+                j.done_s = self.clock() - t0
+                self.used -= j.footprint
+                free_slots.append(j.slot)
+                done.append(j)
             for j in self.engine.poll_ready():
                 building.pop(j.index)
                 j.ready_s = self.clock() - t0
                 if self.k == 0:
-                    self._retire(j, t0, free_slots, done)
+                    retiring[j.index] = j
+                    self.engine.start_finish(j)
                 else:
                     active.append(j)
             if active:
@@ -115,23 +125,17 @@ class Scheduler:
                 for j in active:
                     j.iteration += 1
                     if j.iteration >= self.k:
-                        self._retire(j, t0, free_slots, done)
+                        retiring[j.index] = j
+                        self.engine.start_finish(j)
                     else:
                         still.append(j)
                 active = still
             else:
-                wait = 0.0005
-                if nxt < len(jobs) and not building and not pending:
+                wait = 0.0002 if (building or retiring) else 0.0005
+                if nxt < len(jobs) and not building and not pending and not retiring:
                     wait = max(0.0, min(0.01, jobs[nxt].arrival_s - (self.clock() - t0)))
                 self.engine.idle_wait(wait)
         return done
-
-    def _retire(self, j: Job, t0: float, free_slots, done: List[Job]) -> None:
-        self.engine.finish(j)
-        j.done_s = self.clock() - t0
-        self.used -= j.footprint
-        free_slots.append(j.slot)
-        done.append(j)
 
 
 class GpuEngine:
@@ -153,6 +157,7 @@ class GpuEngine:
         self._todo: queue.Queue = queue.Queue()
         self._ready: queue.Queue = queue.Queue()
         self._err: Optional[BaseException] = None
+        self._retiring: list = []
         # several builders, each with its own stream, so that the host-side
         # latency of one build (launches, two synchronisations) overlaps others
         self._workers = []
@@ -203,12 +208,31 @@ class GpuEngine:
         from . import step_multi
         step_multi([self.ctxs[j.slot] for j in jobs], stream=self.main)
 
-    def finish(self, job: Job) -> None:
+    def start_finish(self, job: Job) -> None:
+        """Copy the result to pinned host memory on the copy stream; the
+        slot is released when the copy's event has completed."""
+        torch = self.torch
         ctx = self.ctxs[job.slot]
-        with self.torch.cuda.stream(self.main):
-            emb = ctx.embedding(stream=self.main)
-            host = emb.to("cpu", non_blocking=False)
-        job.result = host if self.keep_results else None
+        inf = ctx.info()
+        tdt = torch.float32 if inf["dtype"] == 0 else torch.bfloat16
+        host = torch.empty((inf["n"], inf["dim"]), dtype=tdt, pin_memory=True)
+        from . import _lib
+        _lib.check(ctx._lib.cleora_get_embedding(ctx.handle, host.data_ptr(), inf["dim"],
+                                                 inf["dtype"], ctypes.c_void_p(self.main.cuda_stream)))
+        ev = torch.cuda.Event()
+        ev.record(self.main)
+        self._retiring.append((ev, job, host))
+
+    def poll_finished(self) -> List[Job]:
+        out, keep = [], []
+        for ev, job, host in self._retiring:
+            if ev.query():
+                job.result = host if self.keep_results else None
+                out.append(job)
+            else:
+                keep.append((ev, job, host))
+        self._retiring = keep
+        return out
 
     def idle_wait(self, seconds: float) -> None:
         if seconds > 0:
@@ -230,7 +254,7 @@ def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", dev
     single context with the plain path (build, init, k iterations, copy)."""
     import torch
 
-    from . import Context
+    from . import Context, _lib
     jobs = sorted(jobs, key=lambda j: (j.arrival_s, j.index))
     out = []
     with Context(device) as ctx:
@@ -244,7 +268,12 @@ def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", dev
             ctx.build_csr(g.n, g.src, g.dst, g.w, directed=g.directed)
             ctx.init(dim, dtype, j.seed)
             ctx.propagate(k)
-            host = ctx.embedding().cpu()
+            # result straight into pinned host memory, as the batched server does
+            tdt = torch.float32 if dtype in ("f32", "float32") else torch.bfloat16
+            host = torch.empty((g.n, dim), dtype=tdt, pin_memory=True)
+            _lib.check(ctx._lib.cleora_get_embedding(ctx.handle, host.data_ptr(), dim,
+                                                     0 if tdt == torch.float32 else 1, None))
+            ctx.sync()
             j.result = host if keep_results else None
             j.done_s = clock() - t0
             out.append(j)

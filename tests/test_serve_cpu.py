@@ -19,6 +19,8 @@ class FakeEngine:
         self.slots = slots
         self.stepped = {}
         self.max_concurrent = 0
+        self.finishing = []
+        self.copy_s = 0.0003
 
     def footprint(self, job):
         return job.m * 10
@@ -42,10 +44,17 @@ class FakeEngine:
             self.stepped[j.index] = self.stepped.get(j.index, 0) + 1
         self.clock.t += self.step_s
 
-    def finish(self, job):
-        self.live_slots.discard(job.slot)
-        self.live_bytes -= self.footprint(job)
-        job.result = ("done", job.index)
+    def start_finish(self, job):
+        self.finishing.append((self.clock.t + self.copy_s, job))
+
+    def poll_finished(self):
+        out = [j for t, j in self.finishing if t <= self.clock.t]
+        self.finishing = [(t, j) for t, j in self.finishing if t > self.clock.t]
+        for job in out:
+            self.live_slots.discard(job.slot)
+            self.live_bytes -= self.footprint(job)
+            job.result = ("done", job.index)
+        return out
 
     def idle_wait(self, s):
         self.clock.t += max(s, 1e-5)
