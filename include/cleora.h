@@ -118,6 +118,36 @@ int cleora_get_embedding(cleora_ctx *ctx, void *dst, int64_t ld, int32_t dst_dty
  * buffer; valid until the next propagate, init, build or destroy. */
 int cleora_embedding_ptr(cleora_ctx *ctx, const void **ptr, int64_t *ld);
 
+/* Device pointer and row stride of T_{t-1}, the embedding one iteration
+ * before the current one (the other ping-pong buffer), valid while the
+ * current iteration is >= 1 and until the next propagate, init, build or
+ * destroy.  Errors: E_STATE (no embedding, or iteration 0). */
+int cleora_previous_embedding_ptr(cleora_ctx *ctx, const void **ptr, int64_t *ld);
+
+/* One iteration of Algorithm 1 for a set of rows against a given
+ * embedding -- the paper's creation of embeddings for nodes added after
+ * the graph was embedded (Section 3.2): each new node is the normalised
+ * weighted average of its neighbours' rows, ideally taken from iteration
+ * I-1.  Chaining calls (feeding new rows back in as columns) gives the
+ * 2-hop reconstruction of Section 5.
+ *   work      a context used as scratch (its graph and embedding are
+ *             replaced)
+ *   n_rows    number of new nodes R >= 1; n_cols: rows of T_in, C >= 1
+ *   n_edges   m >= 0 edges rows[e] -> cols[e] (device int32, rows in
+ *             [0, R), cols in [0, C)); w: device float32 weights or NULL
+ *   T_in      device C x ld_in embedding (dtype), ld_in = dim rounded up to
+ *             a multiple of 16 bytes (the library's own layout); padding
+ *             elements must be zero
+ *   out       device or host R x ld_out (dtype), ld_out >= dim
+ * A row without edges becomes zero.  Result bit-identical to the matching
+ * row of cleora_propagate over a graph holding the same edges.
+ * Errors: E_INVAL, E_INPUT (ids out of range, bad weights), E_NOMEM,
+ * E_DEVICE. */
+int cleora_propagate_rows(cleora_ctx *work, int64_t n_rows, int64_t n_cols, int64_t n_edges,
+                          const int32_t *rows, const int32_t *cols, const float *w,
+                          const void *T_in, int64_t ld_in, int32_t dim, int32_t dtype, void *out,
+                          int64_t ld_out, void *stream);
+
 /* Copy the built CSR into caller device buffers: row_ptr int64[N+1],
  * col int32[nnz], val float32[nnz] (M values), deg float64[N] (D).  Any of
  * them may be NULL.  Sizes come from cleora_info.  Errors: E_STATE. */

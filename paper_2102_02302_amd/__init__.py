@@ -15,7 +15,8 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, DIRECTED, EMPTY_KEEP, F32, CleoraError, load  # noqa: F401
 
-__all__ = ["Context", "embed", "embed_batch", "step_multi", "footprint_bytes", "CleoraError",
+__all__ = ["Context", "embed", "embed_batch", "embed_new_nodes", "step_multi",
+           "footprint_bytes", "CleoraError",
            "F32", "BF16", "DIRECTED", "EMPTY_KEEP", "load"]
 
 
@@ -160,6 +161,43 @@ class Context:
                                                   _stream(stream)))
         return out
 
+    def embedding_ptr(self, previous: bool = False):
+        """(device pointer, row stride) of T_t, or of T_{t-1} when previous."""
+        ptr, ld = ctypes.c_void_p(), ctypes.c_int64()
+        fn = (self._lib.cleora_previous_embedding_ptr if previous
+              else self._lib.cleora_embedding_ptr)
+        _lib.check(fn(self._h, ctypes.byref(ptr), ctypes.byref(ld)))
+        return ptr.value, ld.value
+
+    def propagate_rows(self, n_rows: int, n_cols: int, rows, cols, T_in, dim: int, dtype="f32",
+                       w=None, ld_in: Optional[int] = None, out=None, stream=None):
+        """One Algorithm-1 step for n_rows new rows against T_in (n_cols rows):
+        out[i] = normalise(sum over edges i->b of w * T_in[b] / deg(i)).
+        T_in is a device tensor, or a raw device pointer with ld_in."""
+        torch = _torch()
+        code = _dtype_code(dtype)
+        tdt = torch.float32 if code == F32 else torch.bfloat16
+        r = _dev_i32(rows, self.device)
+        c = _dev_i32(cols, self.device)
+        wt = _dev_f32(w, self.device)
+        epv = 4 if code == F32 else 8
+        ld_pad = (dim + epv - 1) // epv * epv
+        if isinstance(T_in, int):
+            ptr, ld = T_in, ld_in if ld_in is not None else ld_pad
+        else:
+            t = torch.as_tensor(T_in).to(device=self.device, dtype=tdt)
+            if t.shape[1] != ld_pad:
+                t = torch.nn.functional.pad(t[:, :dim], (0, ld_pad - dim))
+            t = t.contiguous()
+            ptr, ld = t.data_ptr(), ld_pad
+            self._keep = [t]
+        if out is None:
+            out = torch.empty((n_rows, dim), dtype=tdt, device=self.device)
+        _lib.check(self._lib.cleora_propagate_rows(
+            self._h, int(n_rows), int(n_cols), int(r.numel()), _ptr(r), _ptr(c), _ptr(wt), ptr,
+            ld, int(dim), code, out.data_ptr(), out.stride(0), _stream(stream)))
+        return out
+
     def csr(self, stream=None) -> dict:
         torch = _torch()
         inf = self.info()
@@ -195,6 +233,24 @@ def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
         ctx.init(dim, dtype, seed)
         ctx.propagate(k)
         return ctx.embedding()
+
+
+def embed_new_nodes(base: Context, n_new: int, new_ids, old_ids, w=None,
+                    previous: bool = True, work: Optional[Context] = None):
+    """Embeddings of nodes added after ``base`` was embedded (Section 3.2):
+    each new node i averages the rows of its existing neighbours (edges
+    new_ids[e] -> old_ids[e], optional weights), from iteration I-1 when
+    ``previous`` (the paper's recommendation), else from iteration I."""
+    inf = base.info()
+    ptr, ld = base.embedding_ptr(previous=previous)
+    own = work is None
+    work = work or Context(base.device.index or 0)
+    try:
+        return work.propagate_rows(n_new, inf["n"], new_ids, old_ids, ptr, inf["dim"],
+                                   inf["dtype"], w=w, ld_in=ld)
+    finally:
+        if own:
+            work.close()
 
 
 def embed_batch(ctx: Context, graphs: Sequence, dim: int, k: int, seeds: Sequence[int],

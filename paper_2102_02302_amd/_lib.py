@@ -24,6 +24,7 @@ _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
+    "cleora_previous_embedding_ptr", "cleora_propagate_rows",
     "cleora_get_csr", "cleora_info", "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
     "cleora_kernel_time", "cleora_embed_batch", "cleora_step_multi", "cleora_last_error",
 ]
@@ -63,6 +64,10 @@ def load() -> ctypes.CDLL:
         "cleora_propagate": (ctypes.c_int, [p, i32, p]),
         "cleora_get_embedding": (ctypes.c_int, [p, p, i64, i32, p]),
         "cleora_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p), ctypes.POINTER(i64)]),
+        "cleora_previous_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p),
+                                                         ctypes.POINTER(i64)]),
+        "cleora_propagate_rows": (ctypes.c_int, [p, i64, i64, i64, p, p, p, p, i64, i32, i32, p,
+                                                 i64, p]),
         "cleora_get_csr": (ctypes.c_int, [p, p, p, p, p, p]),
         "cleora_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32),

@@ -4,8 +4,10 @@
 //
 // Pipeline (caller's stream, one host synchronisation at the end):
 //   1. one 64-bit key per stored entry, key = row << cb | col (cb = bits of
-//      N-1); a loop's second copy and invalid edges get a key above every
-//      valid one; optional float32 weight as payload;
+//      the column count - 1); a loop's second copy and invalid edges get a
+//      key above every valid one; optional float32 weight as payload.  Rows
+//      and columns may number differently (new nodes against existing ones);
+//      undirected graphs are square;
 //   2. stable LSD radix sort of the keys (8-bit digits, reduce-then-scan:
 //      per-tile digit counts, one device scan, stable scatter through LDS) --
 //      no global atomics, so hub rows cost no more than other rows, and
@@ -37,11 +39,12 @@ __device__ __forceinline__ bool weight_ok(float x)
 
 // Keys of the stored entries: entry 2e is edge e as given, entry 2e+1 its
 // reverse (undirected graphs); directed graphs use entry e only.
-__global__ void k_make_keys(int64_t m, int64_t n, const int32_t *__restrict__ src,
-                            const int32_t *__restrict__ dst, const float *__restrict__ w,
-                            int directed, int cb, uint64_t invalid_key,
-                            uint64_t *__restrict__ keys, float *__restrict__ wout,
-                            uint32_t *err, unsigned long long *n_valid)
+__global__ void k_make_keys(int64_t m, int64_t n_rows, int64_t n_cols,
+                            const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                            const float *__restrict__ w, int directed, int cb,
+                            uint64_t invalid_key, uint64_t *__restrict__ keys,
+                            float *__restrict__ wout, uint32_t *err,
+                            unsigned long long *n_valid)
 {
     __shared__ unsigned long long block_valid;
     if (threadIdx.x == 0) block_valid = 0;
@@ -50,7 +53,7 @@ __global__ void k_make_keys(int64_t m, int64_t n, const int32_t *__restrict__ sr
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = src[e], b = dst[e];
-        bool ok = a >= 0 && a < n && b >= 0 && b < n;
+        bool ok = a >= 0 && a < n_rows && b >= 0 && b < n_cols;
         if (!ok) atomicOr(err, ERR_ID);
         float x = 1.0f;
         if (w) {
@@ -315,17 +318,18 @@ int bits_for(int64_t n)
 
 }  // namespace
 
-void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                 const float *w, uint32_t flags, hipStream_t s)
+void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int32_t *src,
+                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s)
 {
     c->has_graph = false;
     c->has_emb = false;
     const int directed = (flags & CLEORA_DIRECTED) ? 1 : 0;
+    if (!directed && n_cols != n) throw Error(CLEORA_E_INVAL, "undirected graphs are square");
     const int64_t total = directed ? m : 2 * m;  // stored entries before merging
     const int64_t tot1 = std::max<int64_t>(total, 1);
-    const int cb = bits_for(n);
-    const int key_bits = 2 * cb + 1;  // row, column, and the bit of the invalid key
-    const uint64_t invalid_key = (uint64_t)1 << (2 * cb);
+    const int cb = bits_for(n_cols), rb = bits_for(n);
+    const int key_bits = rb + cb + 1;  // row, column, and the bit of the invalid key
+    const uint64_t invalid_key = (uint64_t)1 << (rb + cb);
     const uint64_t cmask = ((uint64_t)1 << cb) - 1;
     const int64_t nblk = ceil_div(tot1, RS_TILE);
 
@@ -357,8 +361,9 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const 
 
     CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
     if (m > 0) {
-        k_make_keys<<<grid_for(m, 256, 65536), 256, 0, s>>>(m, n, src, dst, w, directed, cb,
-                                                            invalid_key, keys, wa, err, n_valid);
+        k_make_keys<<<grid_for(m, 256, 65536), 256, 0, s>>>(m, n, n_cols, src, dst, w, directed,
+                                                            cb, invalid_key, keys, wa, err,
+                                                            n_valid);
         CLEORA_LAUNCH_CHECK();
     }
     // stable LSD radix sort of the keys (and weights)
@@ -411,6 +416,7 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const 
     }
     c->nnz = c->h_small[1];
     c->n = n;
+    c->n_cols = n_cols;
     c->m_in = m;
     c->flags = flags;
     c->has_graph = true;

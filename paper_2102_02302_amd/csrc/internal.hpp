@@ -80,7 +80,7 @@ struct cleora_ctx {
 
     // graph (CSR of M)
     bool has_graph = false;
-    int64_t n = 0, nnz = 0, m_in = 0;
+    int64_t n = 0, n_cols = 0, nnz = 0, m_in = 0;
     uint32_t flags = 0;
     cleora::DevBuf rp, col, val, deg;
 
@@ -112,8 +112,9 @@ struct cleora_ctx {
 
 namespace cleora {
 // CSR build from edges already in device memory (build_csr.hip).
-void build_graph(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                 const float *w, uint32_t flags, hipStream_t s);
+// Rows [0, n) and columns [0, n_cols); undirected graphs need n_cols == n.
+void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int32_t *src,
+                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s);
 // Propagation schedule for the current graph and chunk (propagate.hip).
 void plan_schedule(cleora_ctx *c, hipStream_t s);
 // Fill the two per-parity step descriptors of a context.

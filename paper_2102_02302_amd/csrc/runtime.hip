@@ -280,7 +280,7 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
     if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
     DeviceGuard g(c->device);
     drop_graphs(c);
-    cleora::build_graph(c, n, m, src, dst, w, flags, cleora::as_stream(stream));
+    cleora::build_graph(c, n, n, m, src, dst, w, flags, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
 }
@@ -341,6 +341,64 @@ int cleora_embedding_ptr(cleora_ctx *c, const void **ptr, int64_t *ld)
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
     *ptr = c->E[c->cur].p;
     if (ld) *ld = c->ld;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_previous_embedding_ptr(cleora_ctx *c, const void **ptr, int64_t *ld)
+{
+    ABI_BEGIN
+    if (!c || !ptr) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (!c->has_emb || c->iteration < 1)
+        return fail(CLEORA_E_STATE, "no previous iteration (propagate at least once)");
+    *ptr = c->E[c->cur ^ 1].p;
+    if (ld) *ld = c->ld;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t m,
+                          const int32_t *rows, const int32_t *cols, const float *w,
+                          const void *T_in, int64_t ld_in, int32_t dim, int32_t dtype, void *out,
+                          int64_t ld_out, void *stream)
+{
+    ABI_BEGIN
+    if (!c || !T_in || !out) return fail(CLEORA_E_INVAL, "NULL argument");
+    check_graph_sizes(n_rows, m);
+    check_graph_sizes(n_cols, 0);
+    if (m > 0 && (!rows || !cols)) return fail(CLEORA_E_INVAL, "rows/cols is NULL");
+    check_dim(dim, dtype);
+    if (ld_in != padded_ld(dim, dtype))
+        return fail(CLEORA_E_INVAL, "ld_in must be dim rounded up to a multiple of 16 bytes");
+    if (ld_out < dim) return fail(CLEORA_E_INVAL, "ld_out < dim");
+    if ((reinterpret_cast<uintptr_t>(T_in) & 15) != 0)
+        return fail(CLEORA_E_INVAL, "T_in must be 16-byte aligned");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    drop_graphs(c);
+    cleora::build_graph(c, n_rows, n_cols, m, rows, cols, w, CLEORA_DIRECTED, s);
+    c->dim = dim;
+    c->dtype = dtype;
+    c->ld = (int32_t)ld_in;
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_split(c->ld, dtype);
+    const size_t ebytes = (size_t)n_rows * (size_t)c->ld * elem_size(dtype);
+    c->E[1].ensure(ebytes);
+    cleora::plan_schedule(c, s);
+    c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
+    StepDesc d = cleora::host_desc(c, 0);
+    d.Ein = T_in;
+    d.Eout = c->E[1].p;
+    c->desc.ensure(sizeof(StepDesc) * 2);
+    CLEORA_HIP(hipMemcpyAsync(c->desc.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    const cleora::Variant v = cleora::choose_variant(dtype, c->ld);
+    cleora::launch_spmm(v, d, s);
+    if (c->n_long > 0) cleora::launch_combine(v, c->desc.as<StepDesc>(), 1, c->n_long, s);
+    const size_t es = elem_size(dtype);
+    CLEORA_HIP(hipMemcpy2DAsync(out, (size_t)ld_out * es, c->E[1].p, (size_t)c->ld * es,
+                                (size_t)dim * es, (size_t)n_rows, hipMemcpyDefault, s));
+    // the descriptor above lives on this stack frame
+    CLEORA_HIP(hipStreamSynchronize(s));
+    c->has_emb = false;  // the scratch context holds no propagatable embedding
     return CLEORA_OK;
     ABI_END
 }
@@ -500,7 +558,7 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
                               hipMemcpyHostToDevice, s));
     CLEORA_HIP(hipMemcpyAsync(d_seeds, seeds.data(), sizeof(uint64_t) * seeds.size(),
                               hipMemcpyHostToDevice, s));
-    cleora::build_graph(c, N, M, osrc, odst, ow, flags, s);  // synchronises
+    cleora::build_graph(c, N, N, M, osrc, odst, ow, flags, s);  // synchronises
     setup_embedding(c, dim, dtype, s);
     cleora::launch_init(dtype, c->E[0].p, N, dim, c->ld, d_row0, d_seeds, n_graphs, 0, s);
     c->has_emb = true;
