@@ -186,6 +186,43 @@ int cleora_set_timing(cleora_ctx *ctx, int on);
 int cleora_kernel_time(cleora_ctx *ctx, double *spmm_ms, int64_t *spmm_launches,
                        double *combine_ms, int64_t *combine_launches);
 
+/* ------------------------------------------ chunks (Algorithm 1 merge) */
+
+/* Graphs processed in Q chunks (Algorithm 1): each chunk is an edge subset
+ * embedded on the nodes it touches, and the chunk embeddings are merged
+ * per node with weights w_qv = occurrences of v in chunk q / occurrences of
+ * v in all chunks (occurrences = the node's stored entries before repeated
+ * pairs are merged).
+ *
+ * cleora_build_chunk: like cleora_build_csr for the edges of one chunk of a
+ * graph with n_global nodes (ids in [0, n_global)), but the CSR covers only
+ * the touched nodes, numbered in increasing global id; the next
+ * cleora_init keys each row's T_0 by its *global* id, so all chunks start
+ * from the same vectors.  Errors: as cleora_build_csr; E_INVAL for a chunk
+ * without edges. */
+int cleora_build_chunk(cleora_ctx *ctx, int64_t n_global, int64_t n_edges, const int32_t *src,
+                       const int32_t *dst, const float *w, uint32_t flags, void *stream);
+
+/* Touched nodes of the chunk: *n_local, and optionally (device buffers of
+ * n_local entries) their global ids and occurrence counts.
+ * Errors: E_STATE (not a chunk). */
+int cleora_chunk_info(cleora_ctx *ctx, int64_t *n_local, int32_t *ids, float *occ,
+                      void *stream);
+
+/* acc[v][j] += occ(v) * T[v][j] and wsum[v] += occ(v) for every touched
+ * node v of the chunk (current embedding of ctx).  acc: device float32
+ * n_global x ld_acc (ld_acc >= dim), wsum: device float32[n_global], both
+ * zeroed by the caller before the first chunk.  Chunks merged on one stream
+ * one after another give deterministic sums.  Errors: E_STATE, E_INVAL. */
+int cleora_merge_chunk(cleora_ctx *ctx, float *acc, int64_t ld_acc, float *wsum, void *stream);
+
+/* out[v] = acc[v] / wsum[v] (zero where wsum is 0), n_global x dim into out
+ * (device, row stride ld_out, CLEORA_F32 or CLEORA_BF16) on `device`.
+ * Errors: E_INVAL, E_DEVICE. */
+int cleora_merge_finish(int device, const float *acc, int64_t ld_acc, const float *wsum,
+                        int64_t n_global, int32_t dim, void *out, int64_t ld_out,
+                        int32_t out_dtype, void *stream);
+
 /* ------------------------------------------------------ batched form */
 
 /* One graph of a batch.  Pointers are device pointers as in

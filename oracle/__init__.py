@@ -11,6 +11,8 @@ Functions follow the paper (arXiv 2102.02302):
   * ``init``            -- T_0 ~ U(-1, 1) (Section 3.2)
   * ``propagate``       -- I iterations of multiply + row L2 normalise
                            (Algorithm 1)
+  * ``embed_chunked``   -- Algorithm 1's chunks and weighted merge
+  * ``t1_rows``         -- the first iteration for sampled rows, from the seed
 """
 
 from __future__ import annotations
@@ -59,6 +61,8 @@ def _load():
         lib.oracle_uniform.argtypes = [u64, i64, i32, i32]
         lib.oracle_init.restype = None
         lib.oracle_init.argtypes = [u64, i64, i64, i32, p]
+        lib.oracle_init_ids.restype = None
+        lib.oracle_init_ids.argtypes = [u64, p, i64, i32, p]
         lib.oracle_entry_bound.restype = i64
         lib.oracle_entry_bound.argtypes = [i64, ctypes.c_int]
         lib.oracle_build_adjacency.restype = ctypes.c_int
@@ -217,6 +221,43 @@ def t1_rows(g, rows: np.ndarray, d: int, seed: int, flags: int = 0) -> np.ndarra
     out = np.empty((rows.size, d), np.float64)
     _load().oracle_t1_rows(rows.size, _ptr(rows), d, seed & (2**64 - 1), _ptr(sub.row_ptr),
                            _ptr(sub.col), _ptr(sub.aval), _ptr(out), flags)
+    return out
+
+
+def init_ids(seed: int, ids: np.ndarray, d: int) -> np.ndarray:
+    """T_0 rows of the given global ids."""
+    ids = np.ascontiguousarray(ids, np.int32)
+    T = np.empty((ids.size, d), np.float64)
+    _load().oracle_init_ids(seed & (2**64 - 1), _ptr(ids), ids.size, d, _ptr(T))
+    return T
+
+
+def embed_chunked(g, chunks, d: int, k: int, seed: int, flags: int = 0) -> np.ndarray:
+    """Algorithm 1 with Q chunks: ``chunks`` lists the edge indices of each
+    chunk.  Chunk q is embedded on the nodes its edges touch (T_0 rows of
+    their global ids); node v's result is sum_q w_qv T^q_v with
+    w_qv = occ_q(v) / sum_q occ_q(v), occ_q(v) = v's stored entries in chunk
+    q before repeated pairs are merged."""
+    acc = np.zeros((g.n, d))
+    wsum = np.zeros(g.n)
+    for idx in chunks:
+        src, dst = g.src[idx], g.dst[idx]
+        w = None if g.w is None else g.w[idx]
+        nodes = np.unique(np.concatenate([src, dst]))
+        lid = np.full(g.n, -1, np.int64)
+        lid[nodes] = np.arange(nodes.size)
+        ls, ld = lid[src].astype(np.int32), lid[dst].astype(np.int32)
+        adj = build_adjacency(nodes.size, ls, ld, w, g.directed)
+        mval, _ = transition(adj)
+        Tq = propagate(adj, mval, init_ids(seed, nodes, d), k, flags)
+        occ = np.bincount(ls, minlength=nodes.size).astype(np.float64)
+        if not g.directed:
+            occ += np.bincount(ld[ls != ld], minlength=nodes.size)
+        acc[nodes] += occ[:, None] * Tq
+        wsum[nodes] += occ
+    out = np.zeros_like(acc)
+    nz = wsum > 0
+    out[nz] = acc[nz] / wsum[nz, None]
     return out
 
 

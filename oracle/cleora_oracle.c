@@ -70,6 +70,16 @@ void oracle_init(uint64_t seed, int64_t row0, int64_t n, int32_t d, double *T)
             T[i * d + j] = oracle_uniform(seed, row0 + i, d, j);
 }
 
+/* T_0 rows for arbitrary global ids: row i of T is T_0 row ids[i]. */
+void oracle_init_ids(uint64_t seed, const int32_t *ids, int64_t n, int32_t d, double *T)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; i++)
+        for (int32_t j = 0; j < d; j++)
+            T[i * d + j] = oracle_uniform(seed, ids[i], d, j);
+}
+
 /* ------------------------------------------------------ adjacency build */
 
 typedef struct {

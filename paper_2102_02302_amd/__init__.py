@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, DIRECTED, EMPTY_KEEP, F32, CleoraError, load  # noqa: F401
 
-__all__ = ["Context", "embed", "embed_batch", "embed_new_nodes", "step_multi",
+__all__ = ["Context", "embed", "embed_batch", "embed_chunked", "embed_new_nodes", "step_multi",
            "footprint_bytes", "CleoraError",
            "F32", "BF16", "DIRECTED", "EMPTY_KEEP", "load"]
 
@@ -198,6 +198,23 @@ class Context:
             ld, int(dim), code, out.data_ptr(), out.stride(0), _stream(stream)))
         return out
 
+    def build_chunk(self, n_global: int, src, dst, w=None, directed: bool = False,
+                    stream=None) -> "Context":
+        """CSR of one chunk of a larger graph, on the nodes its edges touch."""
+        s = _dev_i32(src, self.device)
+        d = _dev_i32(dst, self.device)
+        wt = _dev_f32(w, self.device)
+        _lib.check(self._lib.cleora_build_chunk(self._h, int(n_global), int(s.numel()), _ptr(s),
+                                                _ptr(d), _ptr(wt), DIRECTED if directed else 0,
+                                                _stream(stream)))
+        self._keep = [s, d, wt]
+        return self
+
+    def merge_chunk(self, acc, wsum, stream=None) -> None:
+        """acc[v] += occ(v) * T[v], wsum[v] += occ(v) for the chunk's nodes."""
+        _lib.check(self._lib.cleora_merge_chunk(self._h, acc.data_ptr(), acc.stride(0),
+                                                wsum.data_ptr(), _stream(stream)))
+
     def csr(self, stream=None) -> dict:
         torch = _torch()
         inf = self.info()
@@ -251,6 +268,33 @@ def embed_new_nodes(base: Context, n_new: int, new_ids, old_ids, w=None,
     finally:
         if own:
             work.close()
+
+
+def embed_chunked(g, chunks, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0):
+    """Algorithm 1 with chunks: ``chunks`` is a list of edge-index arrays (or
+    an int Q: Q contiguous edge ranges).  Each chunk is embedded on its own
+    nodes, then the chunk embeddings are merged per node, weighted by the
+    node's occurrences in each chunk."""
+    import numpy as np
+    torch = _torch()
+    if isinstance(chunks, int):
+        chunks = np.array_split(np.arange(g.m), chunks)
+    dev = torch.device("cuda", device)
+    acc = torch.zeros((g.n, dim), dtype=torch.float32, device=dev)
+    wsum = torch.zeros(g.n, dtype=torch.float32, device=dev)
+    with Context(device) as ctx:
+        for idx in chunks:
+            w = None if g.w is None else g.w[idx]
+            ctx.build_chunk(g.n, g.src[idx], g.dst[idx], w, g.directed)
+            ctx.init(dim, dtype, seed).propagate(k)
+            ctx.merge_chunk(acc, wsum)
+    code = _dtype_code(dtype)
+    out = torch.empty((g.n, dim), dtype=torch.float32 if code == F32 else torch.bfloat16,
+                      device=dev)
+    _lib.check(load().cleora_merge_finish(device, acc.data_ptr(), acc.stride(0),
+                                          wsum.data_ptr(), g.n, dim, out.data_ptr(),
+                                          out.stride(0), code, _stream(None)))
+    return out
 
 
 def embed_batch(ctx: Context, graphs: Sequence, dim: int, k: int, seeds: Sequence[int],

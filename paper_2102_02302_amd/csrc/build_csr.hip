@@ -248,6 +248,30 @@ __global__ void k_rowptr_search(int64_t n, const int64_t *__restrict__ nnz_p,
     }
 }
 
+// occ[r] = stored entries of row r before repeated pairs are merged (the
+// row's endpoint occurrences in the edge list), by binary search over the
+// n_valid sorted keys.
+__global__ void k_row_counts(int64_t n, const unsigned long long *__restrict__ n_valid,
+                             const uint64_t *__restrict__ keys, int cb, float *__restrict__ occ)
+{
+    const int64_t nv = (int64_t)*n_valid;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t bound[2];
+        for (int q = 0; q < 2; ++q) {
+            const uint64_t target = (uint64_t)(r + q) << cb;
+            int64_t lo = 0, hi = nv;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (keys[mid] >= target) hi = mid;
+                else lo = mid + 1;
+            }
+            bound[q] = lo;
+        }
+        occ[r] = (float)(bound[1] - bound[0]);
+    }
+}
+
 // deg(a) and M values; rows longer than LONG_ROW are listed for the block
 // kernel.  Per-lane partial sums are combined in a fixed butterfly order.
 __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *__restrict__ rp,
@@ -319,7 +343,7 @@ int bits_for(int64_t n)
 }  // namespace
 
 void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int32_t *src,
-                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s)
+                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s, float *occ)
 {
     c->has_graph = false;
     c->has_emb = false;
@@ -388,6 +412,10 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     k_mark_heads<<<gt, 256, 0, s>>>(tot1, n_valid, keys, head);
     CLEORA_LAUNCH_CHECK();
     exclusive_scan(head, tot1, pos, ws, s);
+    if (occ) {
+        k_row_counts<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, n_valid, keys, cb, occ);
+        CLEORA_LAUNCH_CHECK();
+    }
     uint64_t *ukeys = tmpk;  // the other key buffer is free now
     double *esum = c->t_esum.as<double>();
     k_compact<<<gt, 256, 0, s>>>(tot1, n_valid, keys, wa, head, pos, cmask, ukeys,

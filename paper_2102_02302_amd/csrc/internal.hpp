@@ -66,8 +66,19 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
                     hipStream_t s);
 // T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and
 // local indices), or a single graph when n_graphs == 1 and row0 == nullptr.
+// With ids != nullptr, row i uses global index ids[i] (chunks of a graph).
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
-                 const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s);
+                 const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
+                 const int32_t *ids = nullptr);
+
+// Chunks of a graph (chunked.hip).
+void build_chunk(cleora_ctx *c, int64_t n_global, int64_t m, const int32_t *src,
+                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s);
+void launch_merge_rows(int dtype, const void *E, int64_t n, int32_t dim, int32_t ld,
+                       const int32_t *ids, const float *occ, float *acc, int64_t ld_acc,
+                       float *wsum, hipStream_t s);
+void launch_merge_finish(const float *acc, int64_t ld_acc, const float *wsum, int64_t n,
+                         int32_t dim, void *out, int64_t ld_out, int out_dtype, hipStream_t s);
 void launch_widen_bf16(const void *src, int64_t n, int32_t dim, int32_t ld_src, float *dst,
                        int64_t ld_dst, hipStream_t s);
 
@@ -83,6 +94,10 @@ struct cleora_ctx {
     int64_t n = 0, n_cols = 0, nnz = 0, m_in = 0;
     uint32_t flags = 0;
     cleora::DevBuf rp, col, val, deg;
+    // a chunk of a larger graph: local row -> global node, entry counts
+    bool is_chunk = false;
+    int64_t n_global = 0;
+    cleora::DevBuf chunk_ids, chunk_occ, t_local;
 
     // embedding
     bool has_emb = false;
@@ -113,8 +128,10 @@ struct cleora_ctx {
 namespace cleora {
 // CSR build from edges already in device memory (build_csr.hip).
 // Rows [0, n) and columns [0, n_cols); undirected graphs need n_cols == n.
+// With occ != nullptr, occ[r] receives row r's entry count before merging.
 void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int32_t *src,
-                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s);
+                 const int32_t *dst, const float *w, uint32_t flags, hipStream_t s,
+                 float *occ = nullptr);
 // Propagation schedule for the current graph and chunk (propagate.hip).
 void plan_schedule(cleora_ctx *c, hipStream_t s);
 // Fill the two per-parity step descriptors of a context.

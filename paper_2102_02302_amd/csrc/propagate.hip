@@ -58,7 +58,7 @@ __device__ __forceinline__ float uniform_entry(uint64_t seed, int64_t i, int32_t
 template <typename T>
 __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
                        const int64_t *__restrict__ row0, const uint64_t *__restrict__ seeds,
-                       int n_graphs, uint64_t seed0)
+                       int n_graphs, uint64_t seed0, const int32_t *__restrict__ ids)
 {
     constexpr int EPV = 16 / sizeof(T);
     const int64_t vpr = ld / EPV;
@@ -79,6 +79,7 @@ __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
             local = row - row0[lo];
             seed = seeds[lo];
         }
+        if (ids) local = ids[row];
         float x[EPV];
 #pragma unroll
         for (int e = 0; e < EPV; ++e) {
@@ -608,17 +609,18 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
 }
 
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
-                 const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s)
+                 const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
+                 const int32_t *ids)
 {
     const int epv = dtype == CLEORA_BF16 ? 8 : 4;
     const int64_t total = n * (ld / epv);
     const unsigned g = grid_for(total, 256, 1 << 16);
     if (dtype == CLEORA_BF16)
         k_init<uint16_t><<<g, 256, 0, s>>>(reinterpret_cast<uint16_t *>(E), n, dim, ld, row0,
-                                           seeds, n_graphs, seed0);
+                                           seeds, n_graphs, seed0, ids);
     else
         k_init<float><<<g, 256, 0, s>>>(reinterpret_cast<float *>(E), n, dim, ld, row0, seeds,
-                                        n_graphs, seed0);
+                                        n_graphs, seed0, ids);
     CLEORA_LAUNCH_CHECK();
 }
 

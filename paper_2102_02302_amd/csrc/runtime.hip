@@ -238,7 +238,7 @@ void cleora_destroy(cleora_ctx *c)
         (void)hipDeviceSynchronize();
         DevBuf *bufs[] = {&c->rp, &c->col, &c->val, &c->deg, &c->E[0], &c->E[1],
                           &c->split_items, &c->bucket_row, &c->long_rows, &c->chunk_base,
-                          &c->partial, &c->desc, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
+                          &c->partial, &c->desc, &c->chunk_ids, &c->chunk_occ, &c->t_local, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
                           &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
                           &c->t_scan, &c->t_small, &c->multi_desc};
         drop_graphs(c);
@@ -280,6 +280,7 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
     if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
     DeviceGuard g(c->device);
     drop_graphs(c);
+    c->is_chunk = false;
     cleora::build_graph(c, n, n, m, src, dst, w, flags, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
@@ -294,7 +295,8 @@ int cleora_init(cleora_ctx *c, int32_t dim, int32_t dtype, uint64_t seed, void *
     DeviceGuard g(c->device);
     hipStream_t s = cleora::as_stream(stream);
     setup_embedding(c, dim, dtype, s);
-    cleora::launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s);
+    cleora::launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s,
+                        c->is_chunk ? c->chunk_ids.as<int32_t>() : nullptr);
     c->has_emb = true;
     return CLEORA_OK;
     ABI_END
@@ -376,6 +378,7 @@ int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t
     DeviceGuard g(c->device);
     hipStream_t s = cleora::as_stream(stream);
     drop_graphs(c);
+    c->is_chunk = false;
     cleora::build_graph(c, n_rows, n_cols, m, rows, cols, w, CLEORA_DIRECTED, s);
     c->dim = dim;
     c->dtype = dtype;
@@ -509,6 +512,68 @@ int cleora_kernel_time(cleora_ctx *c, double *spmm_ms, int64_t *spmm_n, double *
     ABI_END
 }
 
+int cleora_build_chunk(cleora_ctx *c, int64_t n_global, int64_t m, const int32_t *src,
+                       const int32_t *dst, const float *w, uint32_t flags, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    check_graph_sizes(n_global, m);
+    if (m < 1 || !src || !dst) return fail(CLEORA_E_INVAL, "a chunk needs edges");
+    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
+    DeviceGuard g(c->device);
+    drop_graphs(c);
+    cleora::build_chunk(c, n_global, m, src, dst, w, flags, cleora::as_stream(stream));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_chunk_info(cleora_ctx *c, int64_t *n_local, int32_t *ids, float *occ, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (!c->is_chunk || !c->has_graph) return fail(CLEORA_E_STATE, "not a chunk");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    if (n_local) *n_local = c->n;
+    if (ids)
+        CLEORA_HIP(hipMemcpyAsync(ids, c->chunk_ids.p, sizeof(int32_t) * c->n, hipMemcpyDefault, s));
+    if (occ)
+        CLEORA_HIP(hipMemcpyAsync(occ, c->chunk_occ.p, sizeof(float) * c->n, hipMemcpyDefault, s));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_merge_chunk(cleora_ctx *c, float *acc, int64_t ld_acc, float *wsum, void *stream)
+{
+    ABI_BEGIN
+    if (!c || !acc || !wsum) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (!c->is_chunk || !c->has_emb) return fail(CLEORA_E_STATE, "not an embedded chunk");
+    if (ld_acc < c->dim) return fail(CLEORA_E_INVAL, "ld_acc < dim");
+    DeviceGuard g(c->device);
+    cleora::launch_merge_rows(c->dtype, c->E[c->cur].p, c->n, c->dim, c->ld,
+                              c->chunk_ids.as<int32_t>(), c->chunk_occ.as<float>(), acc, ld_acc,
+                              wsum, cleora::as_stream(stream));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_merge_finish(int device, const float *acc, int64_t ld_acc, const float *wsum,
+                        int64_t n_global, int32_t dim, void *out, int64_t ld_out,
+                        int32_t out_dtype, void *stream)
+{
+    ABI_BEGIN
+    if (!acc || !wsum || !out) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (n_global < 1 || dim < 1 || ld_acc < dim || ld_out < dim)
+        return fail(CLEORA_E_INVAL, "bad sizes");
+    if (out_dtype != CLEORA_F32 && out_dtype != CLEORA_BF16)
+        return fail(CLEORA_E_INVAL, "unknown dtype");
+    DeviceGuard g(device);
+    cleora::launch_merge_finish(acc, ld_acc, wsum, n_global, dim, out, ld_out, out_dtype,
+                                cleora::as_stream(stream));
+    return CLEORA_OK;
+    ABI_END
+}
+
 int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graphs,
                        uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
                        void *stream)
@@ -537,6 +602,7 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
     DeviceGuard dg(c->device);
     hipStream_t s = cleora::as_stream(stream);
     drop_graphs(c);
+    c->is_chunk = false;
     // concatenated edge list with node offsets, then the ordinary build
     const size_t ebytes = ((size_t)std::max<int64_t>(M, 1) * (any_w ? 12 : 8) + 255) / 256 * 256;
     c->t_edges.ensure(ebytes + sizeof(int64_t) * (row0.size() + seeds.size()) + 64);

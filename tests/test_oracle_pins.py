@@ -417,3 +417,37 @@ def test_sampled_rows_undirected_and_empty_keep():
     for flags in (0, oracle.EMPTY_KEEP):
         full = oracle.embed(g, 9, 1, 5, flags)
         assert np.allclose(oracle.t1_rows(g, rows, 9, 5, flags), full[rows], atol=1e-15)
+
+
+# --------------------------------------------- chunks (Algorithm 1 merge)
+
+def test_chunked_single_chunk_is_plain():
+    g = gen.random_graph(80, 300, seed=41, weighted=True, loops=True, multi=True)
+    got = oracle.embed_chunked(g, [np.arange(g.m)], 8, 3, 7)
+    want = oracle.embed(g, 8, 3, 7)
+    deg = np.diff(oracle.build_graph(g).row_ptr)
+    assert np.allclose(got[deg > 0], want[deg > 0], atol=1e-15)
+
+
+def test_chunked_components_are_plain():
+    # two disjoint graphs, one chunk each: every node sees its whole
+    # neighbourhood in its chunk, and T_0 is keyed by global id
+    a = gen.random_graph(50, 200, seed=42)
+    b = gen.random_graph(40, 150, seed=43)
+    g = gen.Graph(90, np.concatenate([a.src, b.src + 50]).astype(np.int32),
+                  np.concatenate([a.dst, b.dst + 50]).astype(np.int32), None, False)
+    chunks = [np.arange(a.m), a.m + np.arange(b.m)]
+    assert np.allclose(oracle.embed_chunked(g, chunks, 6, 4, 3), oracle.embed(g, 6, 4, 3),
+                       atol=1e-14)
+
+
+def test_chunked_hand_example():
+    # path 0-1-2 split into {0-1} and {1-2}, k = 1: node 1 occurs once in
+    # each chunk, so it is the mean of normalise(T0[0]) and normalise(T0[2])
+    g = gen.Graph(3, np.array([0, 1], np.int32), np.array([1, 2], np.int32), None, False)
+    T0 = oracle.init(5, 3, 4)
+    nrm = lambda x: x / np.linalg.norm(x)  # noqa: E731
+    got = oracle.embed_chunked(g, [np.array([0]), np.array([1])], 4, 1, 5)
+    assert np.allclose(got[0], nrm(T0[1]), atol=1e-15)
+    assert np.allclose(got[2], nrm(T0[1]), atol=1e-15)
+    assert np.allclose(got[1], (nrm(T0[0]) + nrm(T0[2])) / 2, atol=1e-15)
