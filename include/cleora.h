@@ -186,6 +186,31 @@ int cleora_set_timing(cleora_ctx *ctx, int on);
 int cleora_kernel_time(cleora_ctx *ctx, double *spmm_ms, int64_t *spmm_launches,
                        double *combine_ms, int64_t *combine_launches);
 
+/* ------------------------------------------------ hypergraph expansion */
+
+/* Section 3.2 breaks every hyperedge into ordinary edges before embedding.
+ * Hyperedges come in CSR form on the device: hyperedge h has members
+ * members[offsets[h] .. offsets[h+1]) (int64 offsets, int32 node ids).
+ * The edges are written to src/dst (device int32, `capacity` entries) in a
+ * fixed order, hyperedge by hyperedge; pass src = NULL to get only the
+ * count in *n_edges.  Feed the result to cleora_build_csr as an undirected
+ * graph.  `ctx` provides the device and scratch memory (its graph and
+ * embedding are kept).  Both synchronise the stream.
+ *
+ * Clique expansion: every pair (m_i, m_j), i < j, of a hyperedge with k
+ * members: k(k-1)/2 edges; a member listed twice yields a loop.
+ * Errors: E_INVAL (sizes, capacity below the count), E_DEVICE. */
+int cleora_expand_clique(cleora_ctx *ctx, int64_t n_hyper, const int64_t *offsets,
+                         const int32_t *members, int32_t *src, int32_t *dst, int64_t capacity,
+                         int64_t *n_edges, void *stream);
+
+/* Star expansion: hyperedge h becomes a new node n_nodes + h linked to each
+ * of its members: k edges per hyperedge, n_nodes + n_hyper nodes in all
+ * (must stay below 2^31).  Errors: as above. */
+int cleora_expand_star(cleora_ctx *ctx, int64_t n_nodes, int64_t n_hyper, const int64_t *offsets,
+                       const int32_t *members, int32_t *src, int32_t *dst, int64_t capacity,
+                       int64_t *n_edges, void *stream);
+
 /* ------------------------------------------ chunks (Algorithm 1 merge) */
 
 /* Graphs processed in Q chunks (Algorithm 1): each chunk is an edge subset

@@ -224,6 +224,30 @@ def t1_rows(g, rows: np.ndarray, d: int, seed: int, flags: int = 0) -> np.ndarra
     return out
 
 
+def expand_clique(offsets, members):
+    """Clique expansion (Section 3.2): every pair of members, i < j, of
+    each hyperedge, hyperedge by hyperedge.  Plain loops."""
+    src, dst = [], []
+    for h in range(len(offsets) - 1):
+        mem = list(members[offsets[h]:offsets[h + 1]])
+        for i in range(len(mem)):
+            for j in range(i + 1, len(mem)):
+                src.append(mem[i])
+                dst.append(mem[j])
+    return np.array(src, np.int32), np.array(dst, np.int32)
+
+
+def expand_star(n_nodes, offsets, members):
+    """Star expansion (Section 3.2): hyperedge h becomes node n_nodes + h
+    linked to each member."""
+    src, dst = [], []
+    for h in range(len(offsets) - 1):
+        for m in members[offsets[h]:offsets[h + 1]]:
+            src.append(n_nodes + h)
+            dst.append(m)
+    return np.array(src, np.int32), np.array(dst, np.int32)
+
+
 def init_ids(seed: int, ids: np.ndarray, d: int) -> np.ndarray:
     """T_0 rows of the given global ids."""
     ids = np.ascontiguousarray(ids, np.int32)

@@ -215,6 +215,30 @@ class Context:
         _lib.check(self._lib.cleora_merge_chunk(self._h, acc.data_ptr(), acc.stride(0),
                                                 wsum.data_ptr(), _stream(stream)))
 
+    def expand(self, offsets, members, mode: str = "clique", n_nodes: int = 0, stream=None):
+        """Hyperedges (CSR: offsets int64[H+1], members int32) -> edge list
+        (src, dst) by clique or star expansion (Section 3.2)."""
+        torch = _torch()
+        off = torch.as_tensor(offsets).to(device=self.device, dtype=torch.int64).contiguous()
+        mem = torch.as_tensor(members).to(device=self.device, dtype=torch.int32).contiguous()
+        h = off.numel() - 1
+        n = ctypes.c_int64()
+        if mode == "clique":
+            fn = lambda s_, d_, cap: self._lib.cleora_expand_clique(  # noqa: E731
+                self._h, h, off.data_ptr(), mem.data_ptr(), s_, d_, cap, ctypes.byref(n),
+                _stream(stream))
+        elif mode == "star":
+            fn = lambda s_, d_, cap: self._lib.cleora_expand_star(  # noqa: E731
+                self._h, int(n_nodes), h, off.data_ptr(), mem.data_ptr(), s_, d_, cap,
+                ctypes.byref(n), _stream(stream))
+        else:
+            raise ValueError(mode)
+        _lib.check(fn(None, None, 0))
+        src = torch.empty(max(n.value, 1), dtype=torch.int32, device=self.device)
+        dst = torch.empty(max(n.value, 1), dtype=torch.int32, device=self.device)
+        _lib.check(fn(src.data_ptr(), dst.data_ptr(), src.numel()))
+        return src[:n.value], dst[:n.value]
+
     def csr(self, stream=None) -> dict:
         torch = _torch()
         inf = self.info()

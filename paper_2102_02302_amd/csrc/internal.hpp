@@ -71,6 +71,14 @@ void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const i
                  const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
                  const int32_t *ids = nullptr);
 
+// Hypergraph expansion (expand.hip).  expand_clique returns the edge count
+// (and writes nothing when src is null).
+int64_t expand_clique(int64_t n_hyper, const int64_t *offsets, const int32_t *members,
+                      int32_t *src, int32_t *dst, int64_t capacity, DevBuf &scratch,
+                      int64_t *h_total, hipStream_t s);
+void expand_star(int64_t n_nodes, int64_t n_hyper, const int64_t *offsets,
+                 const int32_t *members, int32_t *src, int32_t *dst, hipStream_t s);
+
 // Chunks of a graph (chunked.hip).
 void build_chunk(cleora_ctx *c, int64_t n_global, int64_t m, const int32_t *src,
                  const int32_t *dst, const float *w, uint32_t flags, hipStream_t s);
@@ -97,7 +105,7 @@ struct cleora_ctx {
     // a chunk of a larger graph: local row -> global node, entry counts
     bool is_chunk = false;
     int64_t n_global = 0;
-    cleora::DevBuf chunk_ids, chunk_occ, t_local;
+    cleora::DevBuf chunk_ids, chunk_occ, t_local, t_expand;
 
     // embedding
     bool has_emb = false;

@@ -238,7 +238,7 @@ void cleora_destroy(cleora_ctx *c)
         (void)hipDeviceSynchronize();
         DevBuf *bufs[] = {&c->rp, &c->col, &c->val, &c->deg, &c->E[0], &c->E[1],
                           &c->split_items, &c->bucket_row, &c->long_rows, &c->chunk_base,
-                          &c->partial, &c->desc, &c->chunk_ids, &c->chunk_occ, &c->t_local, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
+                          &c->partial, &c->desc, &c->chunk_ids, &c->chunk_occ, &c->t_local, &c->t_expand, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
                           &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
                           &c->t_scan, &c->t_small, &c->multi_desc};
         drop_graphs(c);
@@ -508,6 +508,49 @@ int cleora_kernel_time(cleora_ctx *c, double *spmm_ms, int64_t *spmm_n, double *
     c->ev_spmm.clear();
     c->ev_comb.clear();
     c->ev_next = 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_expand_clique(cleora_ctx *c, int64_t n_hyper, const int64_t *offsets,
+                         const int32_t *members, int32_t *src, int32_t *dst, int64_t capacity,
+                         int64_t *n_edges, void *stream)
+{
+    ABI_BEGIN
+    if (!c || !offsets || !n_edges) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (n_hyper < 0) return fail(CLEORA_E_INVAL, "n_hyper < 0");
+    if (src && !dst) return fail(CLEORA_E_INVAL, "NULL dst");
+    if (src && !members && n_hyper > 0) return fail(CLEORA_E_INVAL, "NULL members");
+    DeviceGuard g(c->device);
+    *n_edges = cleora::expand_clique(n_hyper, offsets, members, src, dst, capacity, c->t_expand,
+                                     c->h_small + 5, cleora::as_stream(stream));
+    if (src) CLEORA_HIP(hipStreamSynchronize(cleora::as_stream(stream)));
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_expand_star(cleora_ctx *c, int64_t n_nodes, int64_t n_hyper, const int64_t *offsets,
+                       const int32_t *members, int32_t *src, int32_t *dst, int64_t capacity,
+                       int64_t *n_edges, void *stream)
+{
+    ABI_BEGIN
+    if (!c || !offsets || !n_edges) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (n_hyper < 0 || n_nodes < 0 || n_nodes + n_hyper > 0x7fffffffLL)
+        return fail(CLEORA_E_INVAL, "n_nodes + n_hyper must stay below 2^31");
+    if (src && !dst) return fail(CLEORA_E_INVAL, "NULL dst");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    CLEORA_HIP(hipMemcpyAsync(c->h_small + 5, offsets, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CLEORA_HIP(hipMemcpyAsync(c->h_small + 6, offsets + n_hyper, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
+    CLEORA_HIP(hipStreamSynchronize(s));
+    const int64_t total = c->h_small[6] - c->h_small[5];
+    *n_edges = total;
+    if (!src) return CLEORA_OK;
+    if (total > capacity) return fail(CLEORA_E_INVAL, "output capacity below the edge count");
+    if (total > 0 && !members) return fail(CLEORA_E_INVAL, "NULL members");
+    cleora::expand_star(n_nodes, n_hyper, offsets, members, src, dst, s);
+    CLEORA_HIP(hipStreamSynchronize(s));
     return CLEORA_OK;
     ABI_END
 }

@@ -451,3 +451,34 @@ def test_chunked_hand_example():
     assert np.allclose(got[0], nrm(T0[1]), atol=1e-15)
     assert np.allclose(got[2], nrm(T0[1]), atol=1e-15)
     assert np.allclose(got[1], (nrm(T0[0]) + nrm(T0[2])) / 2, atol=1e-15)
+
+
+# ------------------------------------------------- hypergraph expansion
+
+def test_expansions_of_the_papers_example():
+    # Section 3.1: customer c buys product p in store s -> hyperedge {c,p,s}
+    c, p_, s_ = 0, 1, 2
+    src, dst = oracle.expand_clique([0, 3], [c, p_, s_])
+    assert sorted(zip(src.tolist(), dst.tolist())) == [(c, p_), (c, s_), (p_, s_)]
+    src, dst = oracle.expand_star(3, [0, 3], [c, p_, s_])
+    assert src.tolist() == [3, 3, 3] and dst.tolist() == [c, p_, s_]
+
+
+def test_expansion_sizes():
+    rng = np.random.default_rng(3)
+    sizes = rng.integers(1, 12, 50)
+    offsets = np.concatenate([[0], np.cumsum(sizes)])
+    members = rng.integers(0, 100, offsets[-1])
+    src, _ = oracle.expand_clique(offsets, members)
+    assert src.size == int((sizes * (sizes - 1) // 2).sum())
+    src, _ = oracle.expand_star(100, offsets, members)
+    assert src.size == offsets[-1]
+
+
+def test_clique_expanded_hyperedge_embeds_like_simple_clique():
+    # one hyperedge of 6 distinct members = K_6; k = 1 closed form
+    src, dst = oracle.expand_clique([0, 6], np.arange(6))
+    g = gen.Graph(6, src, dst, None, False)
+    T0 = oracle.init(4, 6, 9)
+    T1 = oracle.embed(g, 9, 1, 4)
+    assert np.allclose(T1, normalise_rows(T0.sum(0)[None, :] - T0), atol=1e-15)
