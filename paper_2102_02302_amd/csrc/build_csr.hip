@@ -30,7 +30,9 @@ constexpr uint32_t ERR_ID = 1u, ERR_WEIGHT = 2u;
 constexpr int RS_THREADS = 256;
 constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block and pass
-constexpr int LONG_ROW = 4096;                  // rows summed by a whole block
+constexpr int LONG_ROW = 4096;                  // rows summed in segments
+
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 __device__ __forceinline__ bool weight_ok(float x)
 {
@@ -38,18 +40,15 @@ __device__ __forceinline__ bool weight_ok(float x)
 }
 
 // Keys of the stored entries: entry 2e is edge e as given, entry 2e+1 its
-// reverse (undirected graphs); directed graphs use entry e only.
+// reverse (undirected graphs); directed graphs use entry e only.  Invalid
+// edges and a loop's second copy get invalid_key, which sorts last; the
+// number of valid entries is found after the sort.
 __global__ void k_make_keys(int64_t m, int64_t n_rows, int64_t n_cols,
                             const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                             const float *__restrict__ w, int directed, int cb,
                             uint64_t invalid_key, uint64_t *__restrict__ keys,
-                            float *__restrict__ wout, uint32_t *err,
-                            unsigned long long *n_valid)
+                            float *__restrict__ wout, uint32_t *err)
 {
-    __shared__ unsigned long long block_valid;
-    if (threadIdx.x == 0) block_valid = 0;
-    __syncthreads();
-    unsigned long long mine = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = src[e], b = dst[e];
@@ -67,7 +66,6 @@ __global__ void k_make_keys(int64_t m, int64_t n_rows, int64_t n_cols,
         if (directed) {
             keys[e] = fwd;
             if (wout) wout[e] = x;
-            mine += ok ? 1 : 0;
         } else {
             const bool rev_ok = ok && a != b;  // a loop is stored once
             keys[2 * e] = fwd;
@@ -76,13 +74,21 @@ __global__ void k_make_keys(int64_t m, int64_t n_rows, int64_t n_cols,
                 wout[2 * e] = x;
                 wout[2 * e + 1] = x;
             }
-            mine += (ok ? 1 : 0) + (rev_ok ? 1 : 0);
         }
     }
-    mine = wave_sum(mine);
-    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&block_valid, mine);
-    __syncthreads();
-    if (threadIdx.x == 0 && block_valid) atomicAdd(n_valid, block_valid);
+}
+
+// n_valid = number of sorted keys below invalid_key (one thread).
+__global__ void k_count_valid(int64_t total, const uint64_t *__restrict__ keys,
+                              uint64_t invalid_key, unsigned long long *n_valid)
+{
+    int64_t lo = 0, hi = total;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] >= invalid_key) hi = mid;
+        else lo = mid + 1;
+    }
+    *n_valid = (unsigned long long)lo;
 }
 
 // Radix pass, step 1: count[d * nblk + b] = keys of tile b with digit d.
@@ -296,34 +302,67 @@ __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *_
     for (int64_t j = lo + lane; j < hi; j += 64) val[j] = (float)(e_u[j] / s);
 }
 
-__global__ __launch_bounds__(1024) void k_rowsum_block(const int32_t *__restrict__ list,
-                                                       const int32_t *__restrict__ count,
-                                                       const int64_t *__restrict__ rp,
-                                                       const double *__restrict__ e_u,
-                                                       float *__restrict__ val,
-                                                       double *__restrict__ deg)
+// Long rows: segment q of a listed row (LONG_ROW entries each) is summed by
+// one wave in a fixed order into seg[...]; k_rowsum_long then adds a row's
+// segment sums in order and writes deg and the M values.  Listed rows get
+// consecutive segment slots from an exclusive scan of their segment counts.
+// nseg[i] = segments of listed row i, zero for i in [count, n).
+__global__ void k_long_segments(int64_t n, const int32_t *__restrict__ list,
+                                const int32_t *__restrict__ count,
+                                const int64_t *__restrict__ rp, int32_t *__restrict__ nseg)
 {
-    __shared__ double ws[16];
-    __shared__ double total;
     const int cnt = *count;
-    for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
-        const int64_t row = list[li];
-        const int64_t lo = rp[row], hi = rp[row + 1];
-        double s = 0.0;
-        for (int64_t j = lo + threadIdx.x; j < hi; j += 1024) s += e_u[j];
-        s = wave_sum(s);
-        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int i = 0; i < 16; ++i) t += ws[i];
-            total = t;
-            deg[row] = t;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = 0;
+        if (i < cnt) {
+            const int64_t r = list[i];
+            v = (int32_t)ceil_div_dev(rp[r + 1] - rp[r], LONG_ROW);
         }
-        __syncthreads();
-        const double d = total;
-        for (int64_t j = lo + threadIdx.x; j < hi; j += 1024) val[j] = (float)(e_u[j] / d);
-        __syncthreads();
+        nseg[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rowsum_segments(
+    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ seg_base, const int64_t *__restrict__ rp,
+    const double *__restrict__ e_u, double *__restrict__ seg)
+{
+    const int cnt = *count;
+    const int64_t nseg_total = cnt > 0 ? seg_base[cnt] : 0;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         q < nseg_total; q += (int64_t)gridDim.x * 4) {
+        int lo = 0, hi = cnt - 1;  // the listed row owning segment q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg_base[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t r = list[lo];
+        const int64_t b = rp[r] + (q - seg_base[lo]) * LONG_ROW;
+        const int64_t e = min(b + (int64_t)LONG_ROW, rp[r + 1]);
+        double acc = 0.0;
+        for (int64_t j = b + lane; j < e; j += 64) acc += e_u[j];
+        acc = wave_sum(acc);
+        if (lane == 0) seg[q] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rowsum_long(
+    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ seg_base, const double *__restrict__ seg,
+    const int64_t *__restrict__ rp, const double *__restrict__ e_u, float *__restrict__ val,
+    double *__restrict__ deg)
+{
+    const int cnt = *count;
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int64_t r = list[i];
+        double d = 0.0;
+        for (int64_t q = seg_base[i]; q < seg_base[i + 1]; ++q) d += seg[q];
+        if (threadIdx.x == 0) deg[r] = d;
+        for (int64_t j = rp[r] + threadIdx.x; j < rp[r + 1]; j += blockDim.x)
+            val[j] = (float)(e_u[j] / d);
     }
 }
 
@@ -362,10 +401,11 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     c->t_tmp.ensure(sizeof(uint64_t) * (size_t)tot1);
     c->t_esum.ensure(sizeof(double) * (size_t)tot1);
     c->t_head.ensure((size_t)tot1);
-    c->t_cnt.ensure(std::max(sizeof(int32_t) * 256 * (size_t)nblk, sizeof(int32_t) * (size_t)n));
-    c->t_pos.ensure(sizeof(int64_t) * std::max((size_t)tot1 + 1, 256 * (size_t)nblk + 1));
-    c->t_scan.ensure(sizeof(int64_t) *
-                     scan_workspace_elems(std::max<int64_t>(tot1 + 1, 256 * nblk + 1)));
+    // digit counts of a radix pass, later the long-row list and its segment counts
+    c->t_cnt.ensure(sizeof(int32_t) * std::max(256 * (size_t)nblk, 2 * (size_t)n));
+    const int64_t scan_max = std::max<int64_t>(std::max<int64_t>(tot1 + 1, 256 * nblk + 1), n + 1);
+    c->t_pos.ensure(sizeof(int64_t) * (size_t)scan_max);
+    c->t_scan.ensure(sizeof(int64_t) * scan_workspace_elems(scan_max));
     // weight payload (kept apart from t_edges, which may hold the input edges)
     c->t_wts.ensure(w ? 2 * sizeof(float) * (size_t)tot1 : 256);
     c->rp.ensure(sizeof(int64_t) * ((size_t)n + 1));
@@ -386,8 +426,7 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
     if (m > 0) {
         k_make_keys<<<grid_for(m, 256, 65536), 256, 0, s>>>(m, n, n_cols, src, dst, w, directed,
-                                                            cb, invalid_key, keys, wa, err,
-                                                            n_valid);
+                                                            cb, invalid_key, keys, wa, err);
         CLEORA_LAUNCH_CHECK();
     }
     // stable LSD radix sort of the keys (and weights)
@@ -406,6 +445,10 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
             std::swap(keys, tmpk);
             std::swap(wa, wb);
         }
+    }
+    if (total > 0) {
+        k_count_valid<<<1, 1, 0, s>>>(total, keys, invalid_key, n_valid);
+        CLEORA_LAUNCH_CHECK();
     }
     // merge repeated pairs
     const unsigned gt = grid_for(tot1, 256, 65536);
@@ -430,12 +473,26 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
                                                            c->val.as<float>(), c->deg.as<double>(),
                                                            long_list, long_count);
     CLEORA_LAUNCH_CHECK();
-    k_rowsum_block<<<256, 1024, 0, s>>>(long_list, long_count, c->rp.as<int64_t>(), esum,
-                                        c->val.as<float>(), c->deg.as<double>());
-    CLEORA_LAUNCH_CHECK();
+    {
+        // long rows: per-segment sums, then per-row totals in segment order
+        int32_t *nseg = long_list + n;  // the count buffer holds >= 2n entries
+        int64_t *seg_base = pos;        // merged positions are not needed any more
+        double *seg = reinterpret_cast<double *>(c->t_keys.p);  // sorted keys are done too
+        k_long_segments<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, long_list, long_count,
+                                                                c->rp.as<int64_t>(), nseg);
+        CLEORA_LAUNCH_CHECK();
+        exclusive_scan(nseg, n, seg_base, ws, s);
+        k_rowsum_segments<<<1024, 256, 0, s>>>(long_list, long_count, seg_base,
+                                               c->rp.as<int64_t>(), esum, seg);
+        CLEORA_LAUNCH_CHECK();
+        k_rowsum_long<<<512, 256, 0, s>>>(long_list, long_count, seg_base, seg,
+                                          c->rp.as<int64_t>(), esum, c->val.as<float>(),
+                                          c->deg.as<double>());
+        CLEORA_LAUNCH_CHECK();
+    }
     CLEORA_HIP(hipMemcpyAsync(c->h_small, small, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    CLEORA_HIP(hipMemcpyAsync(c->h_small + 1, pos + tot1, sizeof(int64_t), hipMemcpyDeviceToHost,
-                              s));
+    CLEORA_HIP(hipMemcpyAsync(c->h_small + 1, c->rp.as<int64_t>() + n, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, s));
     CLEORA_HIP(hipStreamSynchronize(s));
     const uint32_t e = (uint32_t)(c->h_small[0] & 0xffffffff);
     if (e) {
