@@ -155,6 +155,9 @@ def parse():
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's packing-size autotuner (run once per graph "
+                         "shape, before the timed steps)")
     ap.add_argument("--served", action="store_true",
                     help="run the served-stream benchmark instead (p50/p99 latency)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -231,6 +234,11 @@ def main():
         ctx.init(dim, dtype, seed=2102)
         ctx.propagate(k)
 
+    tuned = None
+    if not args.no_autotune:
+        step()
+        tuned = ctx.autotune()
+        print(f"[bench] autotune: {tuned}", flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -279,7 +287,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_spmm_norm", "bytes_per_launch": int(spmm_bytes),
                 "avg_launch_ms": round(spmm_ms, 4), "launches": kt["spmm_launches"],
-                "combine_avg_ms": round(comb_ms, 4), "schedule": sched}
+                "combine_avg_ms": round(comb_ms, 4), "schedule": sched, "autotune": tuned}
 
     out = {
         "metric": METRIC,

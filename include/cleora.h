@@ -178,6 +178,18 @@ int cleora_sync(cleora_ctx *ctx, void *stream);
  * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 
+/* Autotuner: time one SpMM + combine step of the current embedding with
+ * each candidate packing size (entries per work item for rows that are not
+ * split: 16 .. the split size, powers of two) and keep the fastest for this
+ * graph.  The choice never changes results -- only which wave handles
+ * which rows -- and the embedding and iteration count are left as they
+ * were.  Choices are cached per (N, nnz, dim, dtype, split size) for the
+ * life of the process, and every later cleora_init of a graph of that
+ * shape, in any context, uses the cached choice.  Outputs (may be
+ * NULL): the chosen packing size and its time per step in ms.
+ * Errors: E_STATE (no embedding), E_DEVICE. */
+int cleora_autotune(cleora_ctx *ctx, int32_t *pack, float *step_ms, void *stream);
+
 /* Kernel timing for measurement: when on, the library records HIP events
  * around every SpMM+normalise launch on the launch stream and accumulates
  * their durations; cleora_kernel_time returns the total milliseconds and

@@ -251,6 +251,13 @@ class Context:
                                             val.data_ptr(), deg.data_ptr(), _stream(stream)))
         return {"row_ptr": rp, "col": col[:nnz], "val": val[:nnz], "deg": deg}
 
+    def autotune(self, stream=None) -> dict:
+        """Pick the fastest packing size for this graph (results unchanged)."""
+        pack, ms = ctypes.c_int32(), ctypes.c_float()
+        _lib.check(self._lib.cleora_autotune(self._h, ctypes.byref(pack), ctypes.byref(ms),
+                                             _stream(stream)))
+        return {"pack": pack.value, "step_ms": ms.value}
+
     # -- measurement
     def set_timing(self, on: bool) -> None:
         _lib.check(self._lib.cleora_set_timing(self._h, 1 if on else 0))

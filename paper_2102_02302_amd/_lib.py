@@ -26,7 +26,7 @@ EXPORTS = [
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
     "cleora_previous_embedding_ptr", "cleora_propagate_rows",
     "cleora_get_csr", "cleora_info", "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
-    "cleora_kernel_time", "cleora_expand_clique", "cleora_expand_star", "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk",
+    "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star", "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk",
     "cleora_merge_finish", "cleora_embed_batch", "cleora_step_multi", "cleora_last_error",
 ]
 
@@ -82,6 +82,8 @@ def load() -> ctypes.CDLL:
                                               ctypes.POINTER(i64),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(i64)]),
+        "cleora_autotune": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
+                                           p]),
         "cleora_expand_clique": (ctypes.c_int, [p, i64, p, p, p, p, i64, ctypes.POINTER(i64), p]),
         "cleora_expand_star": (ctypes.c_int, [p, i64, i64, p, p, p, p, i64, ctypes.POINTER(i64),
                                               p]),

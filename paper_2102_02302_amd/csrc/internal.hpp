@@ -113,7 +113,7 @@ struct cleora_ctx {
     cleora::DevBuf E[2];
 
     // schedule
-    int32_t chunk_req = 0, chunk = 0, pack = 0;
+    int32_t chunk_req = 0, chunk = 0, pack = 0, pack_req = 0;
     int64_t n_split = 0, n_buckets = 0, n_long = 0;
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
 
@@ -142,6 +142,8 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
                  float *occ = nullptr);
 // Propagation schedule for the current graph and chunk (propagate.hip).
 void plan_schedule(cleora_ctx *c, hipStream_t s);
+// Packing size the autotuner chose for a graph of this shape, or 0.
+int32_t tuned_pack(const cleora_ctx *c);
 // Fill the two per-parity step descriptors of a context.
 void write_descs(cleora_ctx *c, hipStream_t s);
 StepDesc host_desc(const cleora_ctx *c, int parity);

@@ -638,7 +638,11 @@ void plan_schedule(cleora_ctx *c, hipStream_t s)
     const int32_t C = c->chunk;  // split size: rows longer than this are split
     // packing size: enough items to keep every SIMD busy several times over
     // (no effect on results: a packed row is summed the same way in any item)
-    c->pack = (int32_t)std::min<int64_t>(C, std::max<int64_t>(16, (c->nnz + n) / 32768));
+    // explicit (autotuner trial) > autotuned for this graph shape > formula
+    const int32_t tuned = c->pack_req > 0 ? c->pack_req : tuned_pack(c);
+    c->pack = tuned > 0
+                  ? (int32_t)std::min<int64_t>(C, tuned)
+                  : (int32_t)std::min<int64_t>(C, std::max<int64_t>(16, (c->nnz + n) / 32768));
     const int32_t P = c->pack;
     c->t_cnt.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
     c->t_head.ensure((size_t)std::max<int64_t>(n, 1));

@@ -1,8 +1,12 @@
 // C ABI of the library: contexts, argument checks, launches, errors.
 // Every entry point catches everything and returns a CLEORA_* status.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -15,6 +19,11 @@ using cleora::StepDesc;
 namespace {
 
 thread_local std::string g_last_error;
+
+// autotuner choices: (N, nnz, dim, dtype, split size) -> (packing size, ms)
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int64_t, int32_t, int32_t, int32_t>, std::pair<int32_t, float>>
+    g_tune_cache;
 
 int fail(int code, const std::string &msg)
 {
@@ -197,6 +206,15 @@ __global__ void k_offset_edges(int64_t m, const int32_t *__restrict__ src,
 }
 
 }  // namespace
+
+namespace cleora {
+int32_t tuned_pack(const cleora_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk));
+    return it == g_tune_cache.end() ? 0 : it->second.first;
+}
+}  // namespace cleora
 
 extern "C" {
 
@@ -469,6 +487,86 @@ int cleora_set_chunk(cleora_ctx *c, int32_t chunk)
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (chunk < 0 || chunk > (1 << 20)) return fail(CLEORA_E_INVAL, "chunk out of range");
     c->chunk_req = chunk;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_autotune(cleora_ctx *c, int32_t *pack, float *step_ms, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding: call cleora_init first");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    const auto key = std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk);
+    float best_ms = -1.0f;
+    int32_t best = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best = it->second.first;
+            best_ms = it->second.second;
+        }
+    }
+    if (best == 0) {
+        hipEvent_t a, b;
+        CLEORA_HIP(hipEventCreate(&a));
+        CLEORA_HIP(hipEventCreate(&b));
+        const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
+        const bool timing = c->timing;
+        c->timing = false;
+        try {
+            for (int32_t p = 16; p <= c->chunk; p *= 2) {
+                c->pack_req = p;
+                cleora::plan_schedule(c, s);
+                c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
+                                  (size_t)c->ld);
+                cleora::write_descs(c, s);
+                // steps read T_t and write the other buffer; cur is not flipped,
+                // so the embedding and iteration count stay as they were
+                const StepDesc d = cleora::host_desc(c, c->cur);
+                auto one = [&]() {
+                    cleora::launch_spmm(v, d, s);
+                    if (c->n_long > 0)
+                        cleora::launch_combine(v, c->desc.as<StepDesc>() + c->cur, 1, c->n_long, s);
+                };
+                one();
+                CLEORA_HIP(hipEventRecord(a, s));
+                for (int r = 0; r < 3; ++r) one();
+                CLEORA_HIP(hipEventRecord(b, s));
+                CLEORA_HIP(hipEventSynchronize(b));
+                float ms = 0;
+                CLEORA_HIP(hipEventElapsedTime(&ms, a, b));
+                ms /= 3.0f;
+                if (std::getenv("CLEORA_TUNE_VERBOSE"))
+                    std::fprintf(stderr, "[cleora autotune] n=%lld nnz=%lld d=%d pack=%d: %.4f ms\n",
+                                 (long long)c->n, (long long)c->nnz, c->dim, p, ms);
+                if (best == 0 || ms < best_ms) {
+                    best = p;
+                    best_ms = ms;
+                }
+            }
+        } catch (...) {
+            c->timing = timing;
+            c->pack_req = 0;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            throw;
+        }
+        c->timing = timing;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = std::make_pair(best, best_ms);
+    }
+    drop_graphs(c);
+    c->pack_req = 0;  // the cache entry now applies to this and later inits
+    cleora::plan_schedule(c, s);
+    c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
+    cleora::write_descs(c, s);
+    if (pack) *pack = best;
+    if (step_ms) *step_ms = best_ms;
     return CLEORA_OK;
     ABI_END
 }

@@ -292,3 +292,22 @@ def test_graph_replays_match_eager(cl):
                 b.propagate(1)
             assert np.array_equal(a.embedding().cpu().numpy(), b.embedding().cpu().numpy()), rep
         assert a.info()["iteration"] == 12
+
+
+def test_autotune_keeps_results(cl):
+    # the packing size only moves rows between waves: same bits before and
+    # after tuning, and the tuned choice is reused by later inits
+    g = gen.chung_lu(40_000, 300_000, 2.1, 70)
+    with cl.Context(0) as a:
+        a.build_graph(g).init(128, "f32", 4).propagate(2)
+        before = a.embedding().cpu().numpy()
+        tuned = a.autotune()
+        assert 16 <= tuned["pack"] <= a.schedule()["chunk"]
+        assert a.schedule()["packed_items"] > 0
+        assert np.array_equal(a.embedding().cpu().numpy(), before)
+        assert a.info()["iteration"] == 2
+        a.propagate(2)
+        after = a.embedding().cpu().numpy()
+    with cl.Context(0) as b:
+        b.build_graph(g).init(128, "f32", 4).propagate(4)
+        assert np.array_equal(b.embedding().cpu().numpy(), after)
