@@ -101,12 +101,16 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
 def served_main(args) -> dict:
     """Served stream: Poisson arrivals of independent Chung-Lu requests
     (N log-uniform in [100, 200k], mean degree U(5, 30), d = 128, k = 4).
-    1. capacity of the continuous-batching server (BF16): every request
-       queued at t = 0;  2. the same requests arriving as a Poisson process
-       at `load` x that capacity, served with continuous batching;  3. the
-       same arrivals served one request at a time by the plain FP32 path."""
+    1. capacity of the continuous-batching server (the library's native
+       server, BF16, co-admitted requests built together as one
+       block-diagonal graph): every request submitted at t = 0;
+    2. the same requests arriving as a Poisson process at `load` x that
+       capacity, served with continuous batching;
+    3. the same arrivals served one request at a time by the plain FP32
+       path.  Results land in device memory in every case; latency is
+       arrival -> result ready."""
     import gen
-    from paper_2102_02302_amd.serve import Job, GpuEngine, Scheduler, latency_stats, one_at_a_time
+    from paper_2102_02302_amd.serve import Job, latency_stats, one_at_a_time, run_native
 
     dim, k = 128, 4
     t0 = time.time()
@@ -120,28 +124,41 @@ def served_main(args) -> dict:
 
     nnz = {r.index: (g.m if g.directed else 2 * g.m) for r, g in zip(trace, graphs)}
     nnz_of = lambda j: nnz[j.index]  # noqa: E731
-    eng = GpuEngine(dim, args.served_dtype, args.slots)
-    try:
-        warm = jobs(0.0)[:min(32, len(graphs))]
-        Scheduler(eng, k, args.slots, args.budget_gib << 30).run(warm)
-        sched = Scheduler(eng, k, args.slots, args.budget_gib << 30)
-        done = sched.run(jobs(0.0))
-        cap = latency_stats(done, k, dim, nnz_of)
-        rate = args.load * cap["req_per_s"]
-        print(f"[served] capacity {cap['req_per_s']} req/s; offered {rate:.1f} req/s", flush=True)
-        sched = Scheduler(eng, k, args.slots, args.budget_gib << 30)
-        done = sched.run(jobs(1.0 / rate))
-        batched = latency_stats(done, k, dim, nnz_of)
-        batched.update({"dtype": args.served_dtype, "max_active": sched.max_active,
-                        "mean_step_size": round(sum(sched.step_sizes) / max(1, len(sched.step_sizes)), 2),
-                        "peak_footprint_gib": round(sched.peak_used / 2**30, 3)})
-    finally:
-        eng.close()
-    base = latency_stats(one_at_a_time(jobs(1.0 / rate), dim, k, "f32"), k, dim, nnz_of)
+    opts = dict(slots=args.slots, budget_bytes=args.budget_gib << 30, builders=args.builders,
+                max_group=args.max_group)
+    run_native(jobs(0.0)[:min(64, len(graphs))], dim, args.served_dtype, k, **opts)  # warm-up
+    cap = latency_stats(run_native(jobs(0.0), dim, args.served_dtype, k, **opts), k, dim, nnz_of)
+    cap.update(run_native.last_stats)
+    rate = args.load * cap["req_per_s"]
+    print(f"[served] capacity {cap['req_per_s']} req/s; offered {rate:.1f} req/s", flush=True)
+    batched = latency_stats(run_native(jobs(1.0 / rate), dim, args.served_dtype, k, **opts),
+                            k, dim, nnz_of)
+    batched.update(run_native.last_stats)
+    batched["dtype"] = args.served_dtype
+    base = latency_stats(one_at_a_time(jobs(1.0 / rate), dim, k, "f32", result_on_device=True),
+                         k, dim, nnz_of)
     base["dtype"] = "f32"
-    return {"requests": len(graphs), "dim": dim, "k": k, "offered_req_per_s": round(rate, 2),
-            "load": args.load, "saturated_capacity": cap, "continuous_batching": batched,
-            "one_at_a_time_f32": base}
+    sweep = []
+    for r in [float(x) for x in args.rates.split(",") if x]:
+        row = {"offered_req_per_s": r}
+        for g in sorted({1, args.max_group}):
+            st = latency_stats(run_native(jobs(1.0 / r), dim, args.served_dtype, k,
+                                          **dict(opts, max_group=g)), k, dim, nnz_of)
+            row[f"group{g}"] = {key: st[key] for key in ("p50_ms", "p99_ms", "req_per_s")}
+            row[f"group{g}"]["groups"] = run_native.last_stats["groups"]
+        st = latency_stats(one_at_a_time(jobs(1.0 / r), dim, k, "f32", result_on_device=True),
+                           k, dim, nnz_of)
+        row["one_at_a_time_f32"] = {key: st[key] for key in ("p50_ms", "p99_ms", "req_per_s")}
+        print(f"[served] rate {r}: {row}", flush=True)
+        sweep.append(row)
+    out = {"requests": len(graphs), "dim": dim, "k": k, "offered_req_per_s": round(rate, 2),
+           "load": args.load, "slots": args.slots, "builders": args.builders,
+           "max_group": args.max_group,
+           "saturated_capacity": cap, "continuous_batching": batched,
+           "one_at_a_time_f32": base}
+    if sweep:
+        out["rate_sweep"] = sweep
+    return out
 
 
 def parse():
@@ -164,7 +181,13 @@ def parse():
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gib", type=int, default=64)
+    ap.add_argument("--builders", type=int, default=8)
+    ap.add_argument("--max-group", type=int, default=16,
+                    help="most requests the server builds together as one block-diagonal graph")
     ap.add_argument("--served-dtype", default="bf16")
+    ap.add_argument("--rates", default="",
+                    help="comma-separated offered rates (req/s): latency at each, grouped and "
+                         "ungrouped, beside one-at-a-time FP32")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="launch one plain device copy of this many GiB first "
                          "(reference kernel for HBM counter scaling)")

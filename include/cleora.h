@@ -291,6 +291,73 @@ int cleora_embed_batch(cleora_ctx *ctx, int32_t n_graphs, const cleora_graph *gr
  * E_STATE, E_DEVICE. */
 int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream);
 
+/* ------------------------------------------------------- served form */
+
+/* A native request server on one device: continuous batching of
+ * independent graphs.  Requests are admitted in submission order, as groups
+ * of up to max_group requests, when a builder thread is free, a slot (a
+ * context) is free and the summed cleora_footprint_bytes of admitted
+ * requests stays within budget_bytes (groups grow with the backlog).
+ * Builder threads pack a group's edges into pinned staging,
+ * copy them to the device once and build the group as one block-diagonal
+ * graph (its CSR and T_0, each member's T_0 rows keyed by its own seed and
+ * local ids) on their own streams, while built groups advance one
+ * iteration per step, all of them in shared launches (as
+ * cleora_step_multi).  A group that reached k iterations is copied out,
+ * member by member, to the `out` buffers asynchronously and its slot reused
+ * after the copies.  Every result is bit-identical to the same graph
+ * embedded alone with cleora_build_csr + cleora_init + cleora_propagate
+ * (Section 3.2: a block-diagonal M propagates each block independently;
+ * the kernels compute each row the same way whatever else is in the
+ * graph).  A group whose build fails on bad input is checked member by
+ * member on the host: the bad members complete with E_INPUT, the rest are
+ * rebuilt and served. */
+typedef struct cleora_server cleora_server;
+
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_edges;
+    const int32_t *src; /* host or device memory, unchanged until completion */
+    const int32_t *dst;
+    const float *w;     /* NULL: unweighted */
+    uint64_t seed;
+    void *out;          /* n_nodes x dim (server dtype), row stride dim; device or
+                           pinned host memory, written when the request completes */
+} cleora_request;
+
+typedef struct {
+    int64_t ticket;
+    int32_t status;     /* CLEORA_OK or the build's error code (e.g. E_INPUT) */
+    double submit_s;    /* seconds since the server was created */
+    double admit_s;
+    double ready_s;
+    double done_s;      /* the result is in `out` */
+} cleora_completion;
+
+/* slots: contexts (groups in flight); builders: build threads; max_group:
+ * most requests built together (1: every request on its own).  flags:
+ * CLEORA_DIRECTED / CLEORA_EMPTY_KEEP for every request.
+ * Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t dtype, int32_t k,
+                         int32_t slots, int64_t budget_bytes, int32_t builders, int32_t max_group,
+                         uint32_t flags);
+/* Thread-safe; returns at once.  Errors: E_INVAL (sizes, a footprint above
+ * the whole budget), E_DEVICE (the server stopped after a device error). */
+int cleora_server_submit(cleora_server *s, const cleora_request *req, int64_t *ticket);
+/* Up to max completions (waiting up to wait_s seconds when none is ready). */
+int cleora_server_poll(cleora_server *s, cleora_completion *out, int32_t max, int32_t *n_out,
+                       double wait_s);
+/* Steps run, request-steps run, most groups in one step, peak admitted
+ * footprint, groups built, requests submitted and not yet polled.  Any
+ * output pointer may be NULL. */
+int cleora_server_stats(cleora_server *s, int64_t *steps, int64_t *stepped, int32_t *max_active,
+                        int64_t *peak_bytes, int64_t *groups, int64_t *in_system);
+/* Seconds since the server was created (the clock of the completions). */
+double cleora_server_now(cleora_server *s);
+/* Stops the threads (requests not yet completed are dropped) and frees
+ * everything.  NULL is ignored. */
+void cleora_server_destroy(cleora_server *s);
+
 /* Message for the last error on this thread ("" if none). */
 const char *cleora_last_error(void);
 

@@ -24,10 +24,13 @@ _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
-    "cleora_previous_embedding_ptr", "cleora_propagate_rows",
-    "cleora_get_csr", "cleora_info", "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
-    "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star", "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk",
-    "cleora_merge_finish", "cleora_embed_batch", "cleora_step_multi", "cleora_last_error",
+    "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
+    "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
+    "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star",
+    "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
+    "cleora_embed_batch", "cleora_step_multi", "cleora_server_create", "cleora_server_submit",
+    "cleora_server_poll", "cleora_server_stats", "cleora_server_now", "cleora_server_destroy",
+    "cleora_last_error",
 ]
 
 
@@ -41,6 +44,18 @@ class Graph(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("seed", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("out", ctypes.c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("ready_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +109,16 @@ def load() -> ctypes.CDLL:
         "cleora_embed_batch": (ctypes.c_int, [p, i32, ctypes.POINTER(Graph), u32, i32, i32, i32,
                                               ctypes.POINTER(p), p]),
         "cleora_step_multi": (ctypes.c_int, [ctypes.POINTER(p), i32, p]),
+        "cleora_server_create": (ctypes.c_int, [ctypes.POINTER(p), ctypes.c_int, i32, i32, i32, i32,
+                                                i64, i32, i32, u32]),
+        "cleora_server_submit": (ctypes.c_int, [p, ctypes.POINTER(Request), ctypes.POINTER(i64)]),
+        "cleora_server_poll": (ctypes.c_int, [p, ctypes.POINTER(Completion), i32,
+                                              ctypes.POINTER(i32), ctypes.c_double]),
+        "cleora_server_stats": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                               ctypes.POINTER(i32), ctypes.POINTER(i64),
+                                               ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "cleora_server_now": (ctypes.c_double, [p]),
+        "cleora_server_destroy": (None, [p]),
         "cleora_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -71,12 +72,22 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    // A regrowth asks for at least 1.5x the old size (the exact size if
+    // that fails), so a buffer reused for slowly growing sizes reallocates
+    // O(log) times: each free waits for the device.
     void ensure(size_t bytes)
     {
         if (bytes <= cap && p) return;
+        const size_t grown = cap ? cap + cap / 2 : 0;
         release();
-        size_t b = bytes ? bytes : 256;
-        hipError_t e = hipMalloc(&p, b);
+        size_t b = std::max<size_t>(bytes, 256);
+        hipError_t e = hipErrorMemoryAllocation;
+        if (grown > b) {
+            e = hipMalloc(&p, grown);
+            if (e == hipSuccess) b = grown;
+            else (void)hipGetLastError();
+        }
+        if (e != hipSuccess) e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
             cap = 0;

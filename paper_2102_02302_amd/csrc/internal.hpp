@@ -2,6 +2,7 @@
 #pragma once
 
 #include <map>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -147,4 +148,17 @@ int32_t tuned_pack(const cleora_ctx *c);
 // Fill the two per-parity step descriptors of a context.
 void write_descs(cleora_ctx *c, hipStream_t s);
 StepDesc host_desc(const cleora_ctx *c, int parity);
+// runtime.hip helpers shared with the server
+void build_and_init(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const float *w, uint32_t flags, int32_t dim, int32_t dtype, uint64_t seed,
+                    hipStream_t s);
+void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s);
+// Several graphs as one block-diagonal graph: their edges concatenated in
+// device memory (local ids, rewritten in place), graph g owning edges
+// [eoff[g], eoff[g+1]) and rows [row0[g], row0[g+1]) and seed seeds[g].
+void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int64_t m_total,
+                          int32_t *src, int32_t *dst, const float *w, const int64_t *d_row0,
+                          const int64_t *d_eoff, const uint64_t *d_seeds, uint32_t flags,
+                          int32_t dim, int32_t dtype, hipStream_t s);
+void set_last_error(const std::string &msg);
 }  // namespace cleora

@@ -216,6 +216,101 @@ int32_t tuned_pack(const cleora_ctx *c)
 }
 }  // namespace cleora
 
+namespace cleora {
+
+// Build + T_0 for one context from device edge arrays (the served form's
+// builder threads call this on their own streams).
+void build_and_init(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                    const float *w, uint32_t flags, int32_t dim, int32_t dtype, uint64_t seed,
+                    hipStream_t s)
+{
+    check_graph_sizes(n, m);
+    check_dim(dim, dtype);
+    drop_graphs(c);
+    c->is_chunk = false;
+    build_graph(c, n, n, m, src, dst, w, flags, s);
+    setup_embedding(c, dim, dtype, s);
+    launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s);
+    c->has_emb = true;
+}
+
+// One iteration for each context in one set of launches; synchronises s.
+void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s)
+{
+    cleora_ctx *c0 = ctxs[0];
+    std::vector<StepDesc> tab((size_t)n);
+    int64_t waves = 0, blocks = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        tab[i] = host_desc(ctxs[i], ctxs[i]->cur);
+        tab[i].wave_begin = waves;
+        tab[i].block_begin = blocks;
+        waves += ctxs[i]->n_split + ctxs[i]->n_buckets;
+        blocks += ctxs[i]->n_long;
+    }
+    c0->multi_desc.ensure(sizeof(StepDesc) * tab.size());
+    CLEORA_HIP(hipMemcpyAsync(c0->multi_desc.p, tab.data(), sizeof(StepDesc) * tab.size(),
+                              hipMemcpyHostToDevice, s));
+    const Variant v = choose_variant(c0->dtype, c0->ld);
+    const StepDesc *d = c0->multi_desc.as<StepDesc>();
+    launch_spmm_multi(v, d, n, waves, s);
+    if (blocks > 0) launch_combine(v, d, n, blocks, s);
+    for (int32_t i = 0; i < n; ++i) {
+        ctxs[i]->cur ^= 1;
+        ctxs[i]->iteration++;
+    }
+    // the descriptor table is host memory read by the copy above
+    CLEORA_HIP(hipStreamSynchronize(s));
+}
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+// Concatenated per-graph edges -> block-diagonal ids, in place: edge e of
+// graph g (edges [eoff[g], eoff[g+1])) gets node offset row0[g]; an id
+// outside [0, n_g) becomes -1, which the build reports.
+__global__ void k_offset_edges_table(int64_t m, int32_t *__restrict__ src,
+                                     int32_t *__restrict__ dst,
+                                     const int64_t *__restrict__ eoff,
+                                     const int64_t *__restrict__ row0, int n_graphs)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_graphs - 1;  // last g with eoff[g] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (eoff[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t n_g = row0[lo + 1] - row0[lo];
+        const int32_t a = src[e], b = dst[e];
+        src[e] = (a >= 0 && a < n_g) ? (int32_t)(a + row0[lo]) : -1;
+        dst[e] = (b >= 0 && b < n_g) ? (int32_t)(b + row0[lo]) : -1;
+    }
+}
+}  // namespace
+
+void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int64_t m_total,
+                          int32_t *src, int32_t *dst, const float *w, const int64_t *d_row0,
+                          const int64_t *d_eoff, const uint64_t *d_seeds, uint32_t flags,
+                          int32_t dim, int32_t dtype, hipStream_t s)
+{
+    check_graph_sizes(n_total, m_total);
+    check_dim(dim, dtype);
+    drop_graphs(c);
+    c->is_chunk = false;
+    if (m_total > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(m_total, 256), 65536);
+        k_offset_edges_table<<<blocks, 256, 0, s>>>(m_total, src, dst, d_eoff, d_row0, n_graphs);
+        CLEORA_LAUNCH_CHECK();
+    }
+    build_graph(c, n_total, n_total, m_total, src, dst, w, flags, s);
+    setup_embedding(c, dim, dtype, s);
+    launch_init(dtype, c->E[0].p, n_total, dim, c->ld, d_row0, d_seeds, n_graphs, 0, s);
+    c->has_emb = true;
+}
+
+}  // namespace cleora
+
 extern "C" {
 
 const char *cleora_last_error(void) { return g_last_error.c_str(); }
@@ -797,31 +892,8 @@ int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream)
         for (int32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return fail(CLEORA_E_INVAL, "context listed twice");
     }
-    cleora_ctx *c0 = ctxs[0];
-    DeviceGuard dg(c0->device);
-    hipStream_t s = cleora::as_stream(stream);
-    std::vector<StepDesc> tab((size_t)n);
-    int64_t waves = 0, blocks = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        tab[i] = cleora::host_desc(ctxs[i], ctxs[i]->cur);
-        tab[i].wave_begin = waves;
-        tab[i].block_begin = blocks;
-        waves += ctxs[i]->n_split + ctxs[i]->n_buckets;
-        blocks += ctxs[i]->n_long;
-    }
-    c0->multi_desc.ensure(sizeof(StepDesc) * tab.size());
-    CLEORA_HIP(hipMemcpyAsync(c0->multi_desc.p, tab.data(), sizeof(StepDesc) * tab.size(),
-                              hipMemcpyHostToDevice, s));
-    const cleora::Variant v = cleora::choose_variant(c0->dtype, c0->ld);
-    const StepDesc *d = c0->multi_desc.as<StepDesc>();
-    cleora::launch_spmm_multi(v, d, n, waves, s);
-    if (blocks > 0) cleora::launch_combine(v, d, n, blocks, s);
-    for (int32_t i = 0; i < n; ++i) {
-        ctxs[i]->cur ^= 1;
-        ctxs[i]->iteration++;
-    }
-    // the descriptor table is host memory read by the copy above
-    CLEORA_HIP(hipStreamSynchronize(s));
+    DeviceGuard dg(ctxs[0]->device);
+    cleora::step_contexts(ctxs, n, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
 }

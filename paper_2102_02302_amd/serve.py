@@ -249,9 +249,11 @@ class GpuEngine:
 
 def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", device: int = 0,
                   keep_results: bool = False,
-                  clock: Callable[[], float] = time.perf_counter) -> List[Job]:
+                  clock: Callable[[], float] = time.perf_counter,
+                  result_on_device: bool = False) -> List[Job]:
     """Baseline: the same arrivals served one request after another by a
-    single context with the plain path (build, init, k iterations, copy)."""
+    single context with the plain path (build, init, k iterations, copy of
+    the result to pinned host memory, or to device memory)."""
     import torch
 
     from . import Context, _lib
@@ -268,9 +270,10 @@ def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", dev
             ctx.build_csr(g.n, g.src, g.dst, g.w, directed=g.directed)
             ctx.init(dim, dtype, j.seed)
             ctx.propagate(k)
-            # result straight into pinned host memory, as the batched server does
+            # result straight into pinned host (or device) memory, as the servers do
             tdt = torch.float32 if dtype in ("f32", "float32") else torch.bfloat16
-            host = torch.empty((g.n, dim), dtype=tdt, pin_memory=True)
+            host = (torch.empty((g.n, dim), dtype=tdt, device=ctx.device) if result_on_device
+                    else torch.empty((g.n, dim), dtype=tdt, pin_memory=True))
             _lib.check(ctx._lib.cleora_get_embedding(ctx.handle, host.data_ptr(), dim,
                                                      0 if tdt == torch.float32 else 1, None))
             ctx.sync()
@@ -291,3 +294,131 @@ def latency_stats(done: Sequence[Job], k: int, dim: int, nnz_of: Callable[[Job],
             "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
             "req_per_s": round(len(done) / span, 2),
             "gedge_dims_per_s": round(edge_dims / span / 1e9, 3), "span_s": round(span, 3)}
+
+
+class NativeServer:
+    """The C++ request server of the library (``cleora_server_*``): the same
+    policy as ``Scheduler``, with native scheduler and builder threads."""
+
+    def __init__(self, dim: int, dtype: str, k: int, slots: int = 64,
+                 budget_bytes: int = 64 << 30, builders: int = 4, device: int = 0,
+                 directed: bool = False, max_group: int = 16):
+        from . import DIRECTED, _dtype_code, _lib
+        self._lib = _lib.load()
+        self._check = _lib.check
+        self._Request, self._Completion = _lib.Request, _lib.Completion
+        self.dim, self.dtype, self.k = dim, dtype, k
+        self.code = _dtype_code(dtype)
+        h = ctypes.c_void_p()
+        self._check(self._lib.cleora_server_create(ctypes.byref(h), device, dim, self.code, k,
+                                                   slots, budget_bytes, builders, max_group,
+                                                   DIRECTED if directed else 0))
+        self._h = h
+        self._keep: Dict[int, tuple] = {}
+
+    def now(self) -> float:
+        return float(self._lib.cleora_server_now(self._h))
+
+    def submit(self, n: int, src, dst, w, seed: int, out) -> int:
+        """src/dst/w: contiguous host (numpy) or device (torch) arrays; out: a
+        device or pinned host tensor of n x dim.  Returns the ticket."""
+        import numpy as np
+
+        def ptr(a):
+            if a is None:
+                return None
+            return a.ctypes.data if isinstance(a, np.ndarray) else a.data_ptr()
+
+        req = self._Request(n, len(src), ptr(src), ptr(dst), ptr(w), seed & (2**64 - 1),
+                            out.data_ptr())
+        t = ctypes.c_int64()
+        self._check(self._lib.cleora_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (src, dst, w, out)
+        return t.value
+
+    def poll(self, max_n: int = 256, wait_s: float = 0.0) -> list:
+        buf = (self._Completion * max_n)()
+        n = ctypes.c_int32()
+        self._check(self._lib.cleora_server_poll(self._h, buf, max_n, ctypes.byref(n), wait_s))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            self._keep.pop(c.ticket, None)
+            out.append((c.ticket, c.status, c.submit_s, c.admit_s, c.ready_s, c.done_s))
+        return out
+
+    def stats(self) -> dict:
+        a, b, d, e, f = (ctypes.c_int64() for _ in range(5))
+        c = ctypes.c_int32()
+        self._check(self._lib.cleora_server_stats(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                  ctypes.byref(c), ctypes.byref(d),
+                                                  ctypes.byref(e), ctypes.byref(f)))
+        return {"steps": a.value, "request_steps": b.value, "max_active_groups": c.value,
+                "peak_footprint_bytes": d.value, "groups": e.value, "in_system": f.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.cleora_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_native(jobs: Sequence[Job], dim: int, dtype: str, k: int, slots: int = 64,
+               budget_bytes: int = 64 << 30, builders: int = 4, device: int = 0,
+               keep_results: bool = False, server: Optional[NativeServer] = None,
+               max_group: int = 16) -> List[Job]:
+    """Serve ``jobs`` (arrival times in seconds from the start) with the
+    native server; results land in device memory.  Job times are relative
+    to the start of the trace; latency = result ready - arrival."""
+    import numpy as np
+    import torch
+    jobs = sorted(jobs, key=lambda j: (j.arrival_s, j.index))
+    tdt = torch.float32 if dtype in ("f32", "float32") else torch.bfloat16
+    dev = torch.device("cuda", device)
+    own = server is None
+    srv = server or NativeServer(dim, dtype, k, slots, budget_bytes, builders, device,
+                                 directed=jobs[0].payload.directed if jobs else False,
+                                 max_group=max_group)
+    arrays, outs = {}, {}
+    for j in jobs:
+        g = j.payload
+        arrays[j.index] = (np.ascontiguousarray(g.src, np.int32),
+                           np.ascontiguousarray(g.dst, np.int32),
+                           None if g.w is None else np.ascontiguousarray(g.w, np.float32))
+        outs[j.index] = torch.empty((g.n, dim), dtype=tdt, device=dev)
+    torch.cuda.synchronize()
+    by_ticket, done = {}, []
+    try:
+        t0 = srv.now()
+
+        def drain(wait):
+            for ticket, status, _s, a, r, d in srv.poll(256, wait):
+                j = by_ticket.pop(ticket)
+                if status != 0:
+                    raise RuntimeError(f"request {j.index} failed with status {status}")
+                j.admitted_s, j.ready_s, j.done_s = a - t0, r - t0, d - t0
+                j.iteration = k
+                if keep_results:
+                    j.result = outs[j.index]
+                done.append(j)
+
+        for j in jobs:
+            while srv.now() - t0 < j.arrival_s:
+                drain(0.0)
+                lag = j.arrival_s - (srv.now() - t0)
+                if lag > 0.0002:
+                    time.sleep(min(lag - 0.0001, 0.002))
+            src, dst, w = arrays[j.index]
+            by_ticket[srv.submit(j.payload.n, src, dst, w, j.seed, outs[j.index])] = j
+        while by_ticket:
+            drain(0.05)
+        run_native.last_stats = srv.stats()
+    finally:
+        if own:
+            srv.close()
+    return done

@@ -63,3 +63,69 @@ def test_one_at_a_time_baseline(cl):
     for j in done:
         want = oracle.embed(j.payload, 32, 4, j.seed)
         assert np.abs(j.result.numpy() - want).max() <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,max_group", [("f32", 1), ("f32", 8), ("bf16", 8)])
+def test_native_server_results_equal_solo(cl, dtype, max_group):
+    from paper_2102_02302_amd.serve import latency_stats, run_native
+    trace = gen.served_trace(30, 1.0, n_lo=100, n_hi=20_000)
+    graphs = gen.materialize(trace)
+    dim, k = 64, 4
+    jobs = jobs_for(trace, graphs, 0.0)
+    # all at t = 0 so that groups of several requests form
+    done = run_native(jobs, dim, dtype, k, slots=3, budget_bytes=1 << 30, builders=2,
+                      keep_results=True, max_group=max_group)
+    assert len(done) == len(jobs)
+    stats = latency_stats(done, k, dim, lambda j: 2 * j.m)
+    print(f"native {dtype} group {max_group}: {stats} {run_native.last_stats}")
+    if max_group == 1:
+        assert run_native.last_stats["max_active_groups"] >= 2, "requests never overlapped"
+    else:
+        assert run_native.last_stats["groups"] < len(jobs), "no request was grouped"
+    for j in done:
+        solo = cl.embed(j.payload, dim, k, j.seed, dtype=dtype)
+        assert torch_equal(j.result, solo), j.index
+
+
+def torch_equal(a, b):
+    import torch
+    return bool(torch.equal(a.view(torch.int16) if a.dtype == torch.bfloat16 else a,
+                            b.view(torch.int16) if b.dtype == torch.bfloat16 else b))
+
+
+@pytest.mark.parametrize("max_group", [1, 4])
+def test_native_server_reports_bad_requests(cl, max_group):
+    """A bad request completes with E_INPUT; the requests built in the same
+    group are still served, with their solo results.  Edge arrays may sit
+    in host or device memory."""
+    import torch
+    from paper_2102_02302_amd import _lib
+    from paper_2102_02302_amd.serve import NativeServer
+    srv = NativeServer(16, "f32", 2, slots=2, budget_bytes=1 << 28, builders=1,
+                       max_group=max_group)
+    try:
+        good = gen.erdos_renyi(50, 100, 3)
+        other = gen.erdos_renyi(70, 300, 4)
+        outs = [torch.empty((n, 16), device="cuda") for n in (50, 50, 70, 50)]
+        bad_dst = good.dst.copy()
+        bad_dst[3] = 50  # outside [0, n)
+        bad_w = np.ones(len(good.src), np.float32)
+        bad_w[7] = 0.0   # zero weights are rejected
+        d_src = torch.as_tensor(other.src, device="cuda")
+        d_dst = torch.as_tensor(other.dst, device="cuda")
+        torch.cuda.synchronize()
+        tickets = [srv.submit(50, good.src, bad_dst, None, 1, outs[0]),
+                   srv.submit(50, good.src, good.dst, None, 1, outs[1]),
+                   srv.submit(70, d_src, d_dst, None, 5, outs[2]),
+                   srv.submit(50, good.src, good.dst, bad_w, 1, outs[3])]
+        got = {}
+        while len(got) < len(tickets):
+            for c in srv.poll(8, 0.5):
+                got[c[0]] = c[1]
+        assert [got[t] for t in tickets] == [_lib.E_INPUT, 0, 0, _lib.E_INPUT]
+        assert torch.equal(outs[1], cl.embed(good, 16, 2, 1))
+        assert torch.equal(outs[2], cl.embed(other, 16, 2, 5))
+        with pytest.raises(cl.CleoraError):
+            srv.submit(0, good.src, good.dst, None, 1, outs[0])
+    finally:
+        srv.close()
