@@ -173,7 +173,7 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the library's packing-size autotuner (run once per graph "
+                    help="skip the library's schedule autotuner (run once per graph "
                          "shape, before the timed steps)")
     ap.add_argument("--served", action="store_true",
                     help="run the served-stream benchmark instead (p50/p99 latency)")

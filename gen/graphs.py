@@ -177,10 +177,10 @@ def random_graph(n: int, m: int, seed: int, directed: bool = False,
 WORKLOADS = {
     "er10k": dict(make=lambda: erdos_renyi(10_000, 50_000, BASE_SEED + 0),
                   dim=128, k=4, dtype="f32",
-                  desc="Erdos-Renyi N=10,000, 50,000 undirected edges, d=128 fp32, k=4"),
+                  desc="Erdos-Renyi N=10,000, 50,000 undirected edges, d=128, k=4"),
     "chunglu1m": dict(make=lambda: chung_lu(1_000_000, 20_000_000, 2.1, BASE_SEED + 1),
                       dim=256, k=4, dtype="f32",
-                      desc="Chung-Lu gamma=2.1, N=1M, 20M undirected edges, d=256 fp32, k=4"),
+                      desc="Chung-Lu gamma=2.1, N=1M, 20M undirected edges, d=256, k=4"),
     "chunglu10m": dict(make=lambda: chung_lu(10_000_000, 200_000_000, 2.2, BASE_SEED + 2),
                        dim=1024, k=5, dtype="f32",
                        desc="Chung-Lu gamma=2.2, N=10M, 200M undirected edges, d=1024, k=5"),
@@ -188,7 +188,7 @@ WORKLOADS = {
                                                     BASE_SEED + 3),
                         dim=512, k=4, dtype="bf16",
                         desc="bipartite 5M users x 1M Zipf(1.1) items, 100M log-normal "
-                             "weighted events, d=512 bf16, k=4"),
+                             "weighted events, d=512, k=4"),
 }
 
 

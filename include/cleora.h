@@ -160,10 +160,12 @@ int cleora_info(cleora_ctx *ctx, int64_t *n_nodes, int64_t *nnz, int32_t *dim, i
 
 /* Propagation schedule planned by the last cleora_init: split size, number
  * of split pieces, rows split into pieces (finished by the combine step),
- * packed work items.  Any pointer may be NULL.
+ * packed work items, packing size, SpMM grid (0: one wave per work item,
+ * m: m x the resident waves).  Any pointer may be NULL.
  * Errors: E_STATE (no embedding). */
 int cleora_schedule_info(cleora_ctx *ctx, int32_t *chunk, int64_t *n_split_chunks,
-                         int64_t *n_split_rows, int64_t *n_packed_items);
+                         int64_t *n_split_rows, int64_t *n_packed_items, int32_t *pack,
+                         int32_t *persistent);
 
 /* Wait for the stream.  Errors: E_DEVICE. */
 int cleora_sync(cleora_ctx *ctx, void *stream);
@@ -178,17 +180,29 @@ int cleora_sync(cleora_ctx *ctx, void *stream);
  * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 
+/* Fix the propagation schedule instead of the autotuned or default one
+ * (takes effect at the next cleora_init; cleora_autotune clears it).
+ * pack: entries per work item for rows that are not split (0: automatic,
+ * else 16 .. 2^20, capped at the split size).  persistent: SpMM grid (-1:
+ * automatic, 0: one wave per work item, m in 1..8: m x the resident waves,
+ * each looping over work items).  Neither changes results.
+ * Errors: E_INVAL (out of range). */
+int cleora_set_schedule(cleora_ctx *ctx, int32_t pack, int32_t persistent);
+
 /* Autotuner: time one SpMM + combine step of the current embedding with
- * each candidate packing size (entries per work item for rows that are not
- * split: 16 .. the split size, powers of two) and keep the fastest for this
- * graph.  The choice never changes results -- only which wave handles
- * which rows -- and the embedding and iteration count are left as they
- * were.  Choices are cached per (N, nnz, dim, dtype, split size) for the
- * life of the process, and every later cleora_init of a graph of that
- * shape, in any context, uses the cached choice.  Outputs (may be
- * NULL): the chosen packing size and its time per step in ms.
- * Errors: E_STATE (no embedding), E_DEVICE. */
-int cleora_autotune(cleora_ctx *ctx, int32_t *pack, float *step_ms, void *stream);
+ * each candidate schedule and keep the fastest for this graph.  Candidates:
+ * packing size (entries per work item for rows that are not split: 16 ..
+ * the split size, powers of two) x SpMM grid (one wave per work item, or a
+ * persistent grid of the resident waves, each looping over work items).
+ * The choice never changes results -- only which wave handles which rows
+ * -- and the embedding and iteration count are left as they were.
+ * Choices are cached per (N, nnz, dim, dtype, split size) for the life of
+ * the process, and every later cleora_init of a graph of that shape, in
+ * any context, uses the cached choice.  Outputs (may be NULL): the chosen
+ * packing size, 1 if the persistent grid won (else 0), and the time per
+ * step in ms.  Errors: E_STATE (no embedding), E_DEVICE. */
+int cleora_autotune(cleora_ctx *ctx, int32_t *pack, int32_t *persistent, float *step_ms,
+                    void *stream);
 
 /* Kernel timing for measurement: when on, the library records HIP events
  * around every SpMM+normalise launch on the launch stream and accumulates

@@ -122,6 +122,11 @@ class Context:
     def set_chunk(self, chunk: int) -> None:
         _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
 
+    def set_schedule(self, pack: int = 0, persistent: int = -1) -> None:
+        """Fix the packing size (0: automatic) and SpMM grid (-1: automatic,
+        0: one wave per item, m: m x the resident waves) for the next init."""
+        _lib.check(self._lib.cleora_set_schedule(self._h, int(pack), int(persistent)))
+
     def init(self, dim: int, dtype="f32", seed: int = 0, stream=None) -> "Context":
         _lib.check(self._lib.cleora_init(self._h, int(dim), _dtype_code(dtype),
                                          int(seed) & (2**64 - 1), _stream(stream)))
@@ -143,12 +148,13 @@ class Context:
                 "iteration": it.value}
 
     def schedule(self) -> dict:
-        chunk = ctypes.c_int32()
+        chunk, pack, persist = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         ns, nl, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.check(self._lib.cleora_schedule_info(self._h, ctypes.byref(chunk), ctypes.byref(ns),
-                                                  ctypes.byref(nl), ctypes.byref(nb)))
+                                                  ctypes.byref(nl), ctypes.byref(nb),
+                                                  ctypes.byref(pack), ctypes.byref(persist)))
         return {"chunk": chunk.value, "split_chunks": ns.value, "split_rows": nl.value,
-                "packed_items": nb.value}
+                "packed_items": nb.value, "pack": pack.value, "persistent": persist.value}
 
     def embedding(self, dtype=None, stream=None):
         """Copy of the current N x dim embedding as a device tensor."""
@@ -252,11 +258,12 @@ class Context:
         return {"row_ptr": rp, "col": col[:nnz], "val": val[:nnz], "deg": deg}
 
     def autotune(self, stream=None) -> dict:
-        """Pick the fastest packing size for this graph (results unchanged)."""
-        pack, ms = ctypes.c_int32(), ctypes.c_float()
-        _lib.check(self._lib.cleora_autotune(self._h, ctypes.byref(pack), ctypes.byref(ms),
-                                             _stream(stream)))
-        return {"pack": pack.value, "step_ms": ms.value}
+        """Pick the fastest packing size and SpMM grid (one wave per item or
+        persistent) for this graph; results are unchanged."""
+        pack, persistent, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        _lib.check(self._lib.cleora_autotune(self._h, ctypes.byref(pack), ctypes.byref(persistent),
+                                             ctypes.byref(ms), _stream(stream)))
+        return {"pack": pack.value, "persistent": bool(persistent.value), "step_ms": ms.value}
 
     # -- measurement
     def set_timing(self, on: bool) -> None:

@@ -25,7 +25,8 @@ EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
     "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
-    "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_timing",
+    "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
+    "cleora_set_timing",
     "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star",
     "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
     "cleora_embed_batch", "cleora_step_multi", "cleora_server_create", "cleora_server_submit",
@@ -89,16 +90,18 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
                                        ctypes.POINTER(i32)]),
         "cleora_schedule_info": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i64),
-                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+                                                ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cleora_sync": (ctypes.c_int, [p, p]),
         "cleora_set_chunk": (ctypes.c_int, [p, i32]),
+        "cleora_set_schedule": (ctypes.c_int, [p, i32, i32]),
         "cleora_set_timing": (ctypes.c_int, [p, ctypes.c_int]),
         "cleora_kernel_time": (ctypes.c_int, [p, ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(i64),
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(i64)]),
-        "cleora_autotune": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float),
-                                           p]),
+        "cleora_autotune": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                           ctypes.POINTER(ctypes.c_float), p]),
         "cleora_expand_clique": (ctypes.c_int, [p, i64, p, p, p, p, i64, ctypes.POINTER(i64), p]),
         "cleora_expand_star": (ctypes.c_int, [p, i64, i64, p, p, p, p, i64, ctypes.POINTER(i64),
                                               p]),

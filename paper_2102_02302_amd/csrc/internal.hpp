@@ -44,7 +44,7 @@ struct StepDesc {
     int32_t ld;
     int32_t chunk;
     uint32_t flags;
-    int32_t pad_;
+    int32_t persist;  // SpMM grid: 0 = one wave per item, m > 0 = m x the resident blocks
 };
 
 // Kernel variant for an embedding layout.
@@ -62,7 +62,9 @@ Variant choose_variant(int dtype, int ld);
 void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s);
 // Several contexts: `descs` is a device table with wave_begin prefixes.
 void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
-                       hipStream_t s);
+                       int32_t persist, hipStream_t s);
+// One-time set-up of a persistent SpMM grid for this variant (no launch).
+void prime_spmm(const Variant &v, int32_t persist);
 void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,
                     hipStream_t s);
 // T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and
@@ -115,6 +117,7 @@ struct cleora_ctx {
 
     // schedule
     int32_t chunk_req = 0, chunk = 0, pack = 0, pack_req = 0;
+    int32_t persist = 0, persist_req = -1;  // SpMM grid (StepDesc::persist); -1: not forced
     int64_t n_split = 0, n_buckets = 0, n_long = 0;
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
 
@@ -145,6 +148,8 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
 void plan_schedule(cleora_ctx *c, hipStream_t s);
 // Packing size the autotuner chose for a graph of this shape, or 0.
 int32_t tuned_pack(const cleora_ctx *c);
+// SpMM grid the autotuner chose for a graph of this shape (0 by default).
+int32_t tuned_persist(const cleora_ctx *c);
 // Fill the two per-parity step descriptors of a context.
 void write_descs(cleora_ctx *c, hipStream_t s);
 StepDesc host_desc(const cleora_ctx *c, int parity);

@@ -380,7 +380,10 @@ __device__ __forceinline__ int64_t wave_id()
 }
 
 // One graph: plain restrict-qualified global pointers, so column/value
-// loads of a wave become scalar loads and gathers global loads.
+// loads of a wave become scalar loads and gathers global loads.  A wave
+// takes items wave, wave + waves in grid, ...: with one wave per item the
+// loop runs once; with a grid of the resident waves only, the kernel is
+// persistent (which of the two is faster is the autotuner's call).
 template <typename T, int G, int VPL, int U>
 __global__ __launch_bounds__(256) void k_spmm_norm(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -389,22 +392,27 @@ __global__ __launch_bounds__(256) void k_spmm_norm(
     const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
     int chunk, uint32_t flags, int cpr)
 {
-    spmm_item<T, G, VPL, U>(wave_id(), rp, col, val, Ein, Eout, partial, split_items, bucket_row,
-                            n_split, n_buckets, ld, chunk, flags, cpr);
+    const int64_t items = n_split + n_buckets, stride = (int64_t)gridDim.x * 4;
+    for (int64_t w = wave_id(); w < items; w += stride)
+        spmm_item<T, G, VPL, U>(w, rp, col, val, Ein, Eout, partial, split_items, bucket_row,
+                                n_split, n_buckets, ld, chunk, flags, cpr);
 }
 
-// Several graphs (continuous batching): each wave finds its graph in the
+// Several graphs (continuous batching): each item's graph is found in the
 // descriptor table.
 template <typename T, int G, int VPL, int U>
 __global__ __launch_bounds__(256) void k_spmm_norm_multi(const StepDesc *__restrict__ descs,
-                                                         int n_desc, int cpr)
+                                                         int n_desc, int64_t items, int cpr)
 {
-    int64_t wave = wave_id();
-    const StepDesc &D = descs[find_desc(descs, n_desc, wave, false)];
-    spmm_item<T, G, VPL, U>(wave - D.wave_begin, D.rp, D.col, D.val,
-                            reinterpret_cast<const uint4 *>(D.Ein),
-                            reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items,
-                            D.bucket_row, D.n_split, D.n_buckets, D.ld, D.chunk, D.flags, cpr);
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    for (int64_t w = wave_id(); w < items; w += stride) {
+        const StepDesc &D = descs[find_desc(descs, n_desc, w, false)];
+        spmm_item<T, G, VPL, U>(w - D.wave_begin, D.rp, D.col, D.val,
+                                reinterpret_cast<const uint4 *>(D.Ein),
+                                reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items,
+                                D.bucket_row, D.n_split, D.n_buckets, D.ld, D.chunk, D.flags,
+                                cpr);
+    }
 }
 
 // Combine the partial sums of a split row in chunk order, normalise, store.
@@ -490,11 +498,29 @@ unsigned grid_for(int64_t items, int threads, int64_t cap = 1 << 20)
     return (unsigned)std::min<int64_t>(g, cap);
 }
 
+// Blocks of `kernel` (256 threads) resident on the whole device at once.
+template <typename K>
+int64_t resident_blocks(K kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    CLEORA_HIP(hipGetDevice(&dev));
+    CLEORA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CLEORA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+    return (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+}
+
 template <typename T, int G, int VPL, int U>
 void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_t waves, int cpr,
-                 hipStream_t s)
+                 int32_t persist, hipStream_t s)
 {
-    const int64_t blocks = ceil_div(waves, 4);
+    int64_t blocks = ceil_div(waves, 4);
+    if (persist > 0) {
+        // per kernel instance, queried once (at init: see prime_spmm); every
+        // device this library runs on is a gfx950
+        static const int64_t res1 = resident_blocks(k_spmm_norm<T, G, VPL, U>);
+        static const int64_t resm = resident_blocks(k_spmm_norm_multi<T, G, VPL, U>);
+        blocks = std::min(blocks, (int64_t)persist * (host ? res1 : resm));
+    }
     if (blocks <= 0) return;
     if (blocks > 0x7fffffffLL) throw Error(CLEORA_E_INVAL, "propagation grid too large");
     if (host) {
@@ -504,30 +530,31 @@ void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_
             reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items, D.bucket_row, D.n_split,
             D.n_buckets, D.ld, D.chunk, D.flags, cpr);
     } else {
-        k_spmm_norm_multi<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, cpr);
+        k_spmm_norm_multi<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, waves,
+                                                                         cpr);
     }
     CLEORA_LAUNCH_CHECK();
 }
 
 template <typename T>
 void spmm_dispatch(const Variant &v, const StepDesc *host, const StepDesc *descs, int n_desc,
-                   int64_t waves, hipStream_t s)
+                   int64_t waves, int32_t persist, hipStream_t s)
 {
     if (v.VPL == 1) {
         switch (v.G) {
-        case 1: return spmm_launch<T, 1, 1, 8>(host, descs, n_desc, waves, v.cpr, s);
-        case 2: return spmm_launch<T, 2, 1, 4>(host, descs, n_desc, waves, v.cpr, s);
-        case 4: return spmm_launch<T, 4, 1, 2>(host, descs, n_desc, waves, v.cpr, s);
-        case 8: return spmm_launch<T, 8, 1, 1>(host, descs, n_desc, waves, v.cpr, s);
-        case 16: return spmm_launch<T, 16, 1, 1>(host, descs, n_desc, waves, v.cpr, s);
+        case 1: return spmm_launch<T, 1, 1, 8>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 2: return spmm_launch<T, 2, 1, 4>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 4: return spmm_launch<T, 4, 1, 2>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 8: return spmm_launch<T, 8, 1, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 16: return spmm_launch<T, 16, 1, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
         default: break;
         }
     } else {
         switch (v.VPL) {
-        case 2: return spmm_launch<T, 1, 2, 4>(host, descs, n_desc, waves, v.cpr, s);
-        case 4: return spmm_launch<T, 1, 4, 2>(host, descs, n_desc, waves, v.cpr, s);
-        case 8: return spmm_launch<T, 1, 8, 1>(host, descs, n_desc, waves, v.cpr, s);
-        case 16: return spmm_launch<T, 1, 16, 1>(host, descs, n_desc, waves, v.cpr, s);
+        case 2: return spmm_launch<T, 1, 2, 4>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 4: return spmm_launch<T, 1, 4, 2>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 8: return spmm_launch<T, 1, 8, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 16: return spmm_launch<T, 1, 16, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
         default: break;
         }
     }
@@ -590,15 +617,26 @@ Variant choose_variant(int dtype, int ld)
 void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s)
 {
     const int64_t waves = one.n_split + one.n_buckets;
-    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, &one, nullptr, 1, waves, s);
-    else spmm_dispatch<float>(v, &one, nullptr, 1, waves, s);
+    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, &one, nullptr, 1, waves, one.persist, s);
+    else spmm_dispatch<float>(v, &one, nullptr, 1, waves, one.persist, s);
+}
+
+// Runs the one-time occupancy queries of a persistent grid now, so that
+// none happens inside a graph capture (no kernel is launched).
+void prime_spmm(const Variant &v, int32_t persist)
+{
+    if (persist <= 0) return;
+    StepDesc none{};
+    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, &none, nullptr, 1, 0, persist, nullptr);
+    else spmm_dispatch<float>(v, &none, nullptr, 1, 0, persist, nullptr);
 }
 
 void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
-                       hipStream_t s)
+                       int32_t persist, hipStream_t s)
 {
-    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, nullptr, descs, n_desc, total_waves, s);
-    else spmm_dispatch<float>(v, nullptr, descs, n_desc, total_waves, s);
+    if (v.dtype == CLEORA_BF16)
+        spmm_dispatch<uint16_t>(v, nullptr, descs, n_desc, total_waves, persist, s);
+    else spmm_dispatch<float>(v, nullptr, descs, n_desc, total_waves, persist, s);
 }
 
 void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,
@@ -640,6 +678,8 @@ void plan_schedule(cleora_ctx *c, hipStream_t s)
     // (no effect on results: a packed row is summed the same way in any item)
     // explicit (autotuner trial) > autotuned for this graph shape > formula
     const int32_t tuned = c->pack_req > 0 ? c->pack_req : tuned_pack(c);
+    c->persist = c->persist_req >= 0 ? c->persist_req : tuned_persist(c);
+    prime_spmm(choose_variant(c->dtype, c->ld), c->persist);
     c->pack = tuned > 0
                   ? (int32_t)std::min<int64_t>(C, tuned)
                   : (int32_t)std::min<int64_t>(C, std::max<int64_t>(16, (c->nnz + n) / 32768));
@@ -698,6 +738,7 @@ StepDesc host_desc(const cleora_ctx *c, int parity)
     d.ld = c->ld;
     d.chunk = c->chunk;
     d.flags = c->flags;
+    d.persist = c->persist;
     return d;
 }
 

@@ -20,10 +20,13 @@ namespace {
 
 thread_local std::string g_last_error;
 
-// autotuner choices: (N, nnz, dim, dtype, split size) -> (packing size, ms)
+// autotuner choices: (N, nnz, dim, dtype, split size) -> schedule and its time
+struct TuneChoice {
+    int32_t pack = 0, persist = 0;
+    float ms = -1.0f;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int64_t, int64_t, int32_t, int32_t, int32_t>, std::pair<int32_t, float>>
-    g_tune_cache;
+std::map<std::tuple<int64_t, int64_t, int32_t, int32_t, int32_t>, TuneChoice> g_tune_cache;
 
 int fail(int code, const std::string &msg)
 {
@@ -212,7 +215,14 @@ int32_t tuned_pack(const cleora_ctx *c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk));
-    return it == g_tune_cache.end() ? 0 : it->second.first;
+    return it == g_tune_cache.end() ? 0 : it->second.pack;
+}
+
+int32_t tuned_persist(const cleora_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk));
+    return it == g_tune_cache.end() ? 0 : it->second.persist;
 }
 }  // namespace cleora
 
@@ -252,7 +262,7 @@ void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s)
                               hipMemcpyHostToDevice, s));
     const Variant v = choose_variant(c0->dtype, c0->ld);
     const StepDesc *d = c0->multi_desc.as<StepDesc>();
-    launch_spmm_multi(v, d, n, waves, s);
+    launch_spmm_multi(v, d, n, waves, c0->persist, s);
     if (blocks > 0) launch_combine(v, d, n, blocks, s);
     for (int32_t i = 0; i < n; ++i) {
         ctxs[i]->cur ^= 1;
@@ -553,11 +563,13 @@ int cleora_info(cleora_ctx *c, int64_t *n, int64_t *nnz, int32_t *dim, int32_t *
 }
 
 int cleora_schedule_info(cleora_ctx *c, int32_t *chunk, int64_t *n_split, int64_t *n_long,
-                         int64_t *n_buckets)
+                         int64_t *n_buckets, int32_t *pack, int32_t *persistent)
 {
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
+    if (pack) *pack = c->pack;
+    if (persistent) *persistent = c->persist;
     if (chunk) *chunk = c->chunk;
     if (n_split) *n_split = c->n_split;
     if (n_long) *n_long = c->n_long;
@@ -586,7 +598,22 @@ int cleora_set_chunk(cleora_ctx *c, int32_t chunk)
     ABI_END
 }
 
-int cleora_autotune(cleora_ctx *c, int32_t *pack, float *step_ms, void *stream)
+int cleora_set_schedule(cleora_ctx *c, int32_t pack, int32_t persistent)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (pack != 0 && (pack < 16 || pack > (1 << 20)))
+        return fail(CLEORA_E_INVAL, "pack must be 0 or in [16, 2^20]");
+    if (persistent < -1 || persistent > 8)
+        return fail(CLEORA_E_INVAL, "persistent must be in [-1, 8]");
+    c->pack_req = pack;
+    c->persist_req = persistent;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *step_ms,
+                    void *stream)
 {
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
@@ -594,74 +621,85 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, float *step_ms, void *stream)
     DeviceGuard g(c->device);
     hipStream_t s = cleora::as_stream(stream);
     const auto key = std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk);
-    float best_ms = -1.0f;
-    int32_t best = 0;
+    TuneChoice best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            best = it->second.first;
-            best_ms = it->second.second;
-        }
+        if (it != g_tune_cache.end()) best = it->second;
     }
-    if (best == 0) {
+    if (best.pack == 0) {
         hipEvent_t a, b;
         CLEORA_HIP(hipEventCreate(&a));
         CLEORA_HIP(hipEventCreate(&b));
         const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
         const bool timing = c->timing;
         c->timing = false;
+        auto restore = [&]() {
+            c->timing = timing;
+            c->pack_req = 0;
+            c->persist_req = -1;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        };
         try {
+            // packing size x grid (one wave per item, or the resident waves
+            // looping over the items)
             for (int32_t p = 16; p <= c->chunk; p *= 2) {
                 c->pack_req = p;
+                c->persist_req = 0;
                 cleora::plan_schedule(c, s);
                 c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
                                   (size_t)c->ld);
                 cleora::write_descs(c, s);
-                // steps read T_t and write the other buffer; cur is not flipped,
-                // so the embedding and iteration count stay as they were
-                const StepDesc d = cleora::host_desc(c, c->cur);
-                auto one = [&]() {
-                    cleora::launch_spmm(v, d, s);
-                    if (c->n_long > 0)
-                        cleora::launch_combine(v, c->desc.as<StepDesc>() + c->cur, 1, c->n_long, s);
-                };
-                one();
-                CLEORA_HIP(hipEventRecord(a, s));
-                for (int r = 0; r < 3; ++r) one();
-                CLEORA_HIP(hipEventRecord(b, s));
-                CLEORA_HIP(hipEventSynchronize(b));
-                float ms = 0;
-                CLEORA_HIP(hipEventElapsedTime(&ms, a, b));
-                ms /= 3.0f;
-                if (std::getenv("CLEORA_TUNE_VERBOSE"))
-                    std::fprintf(stderr, "[cleora autotune] n=%lld nnz=%lld d=%d pack=%d: %.4f ms\n",
-                                 (long long)c->n, (long long)c->nnz, c->dim, p, ms);
-                if (best == 0 || ms < best_ms) {
-                    best = p;
-                    best_ms = ms;
+                for (int32_t persist = 0; persist <= 1; ++persist) {
+                    // steps read T_t and write the other buffer; cur is not
+                    // flipped, so the embedding and iteration count stay as
+                    // they were
+                    StepDesc d = cleora::host_desc(c, c->cur);
+                    d.persist = persist;
+                    auto one = [&]() {
+                        cleora::launch_spmm(v, d, s);
+                        if (c->n_long > 0)
+                            cleora::launch_combine(v, c->desc.as<StepDesc>() + c->cur, 1,
+                                                   c->n_long, s);
+                    };
+                    one();
+                    CLEORA_HIP(hipEventRecord(a, s));
+                    for (int r = 0; r < 3; ++r) one();
+                    CLEORA_HIP(hipEventRecord(b, s));
+                    CLEORA_HIP(hipEventSynchronize(b));
+                    float ms = 0;
+                    CLEORA_HIP(hipEventElapsedTime(&ms, a, b));
+                    ms /= 3.0f;
+                    if (std::getenv("CLEORA_TUNE_VERBOSE"))
+                        std::fprintf(stderr,
+                                     "[cleora autotune] n=%lld nnz=%lld d=%d pack=%d persist=%d: "
+                                     "%.4f ms\n",
+                                     (long long)c->n, (long long)c->nnz, c->dim, p, persist, ms);
+                    if (best.pack == 0 || ms < best.ms) {
+                        best.pack = p;
+                        best.persist = persist;
+                        best.ms = ms;
+                    }
                 }
             }
         } catch (...) {
-            c->timing = timing;
-            c->pack_req = 0;
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+            restore();
             throw;
         }
-        c->timing = timing;
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        restore();
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = std::make_pair(best, best_ms);
+        g_tune_cache[key] = best;
     }
     drop_graphs(c);
     c->pack_req = 0;  // the cache entry now applies to this and later inits
+    c->persist_req = -1;
     cleora::plan_schedule(c, s);
     c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
     cleora::write_descs(c, s);
-    if (pack) *pack = best;
-    if (step_ms) *step_ms = best_ms;
+    if (pack) *pack = best.pack;
+    if (persistent) *persistent = best.persist;
+    if (step_ms) *step_ms = best.ms;
     return CLEORA_OK;
     ABI_END
 }

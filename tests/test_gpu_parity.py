@@ -194,13 +194,17 @@ def test_batch_equals_solo_bitwise(cl):
         assert np.abs(o - oracle_embed(g, 96, 4, s)).max() <= F32_TOL
 
 
-def test_step_multi_equals_solo_bitwise(cl):
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_step_multi_equals_solo_bitwise(cl, persistent):
     graphs = [gen.chung_lu(4000, 30_000, 2.1, 30), gen.erdos_renyi(900, 4000, 31),
               gen.chung_lu(12_000, 90_000, 2.1, 32)]
     ctxs = [cl.Context(0) for _ in graphs]
     try:
         for c, g, s in zip(ctxs, graphs, [1, 2, 3]):
+            # the first context's grid choice applies to the shared launch
+            c.set_schedule(0, persistent)
             c.build_graph(g).init(128, "f32", s)
+            assert c.schedule()["persistent"] == persistent
         ctxs[0].propagate(1)  # requests at different iterations share a step
         for _ in range(3):
             cl.step_multi(ctxs)
@@ -294,6 +298,31 @@ def test_graph_replays_match_eager(cl):
         assert a.info()["iteration"] == 12
 
 
+@pytest.mark.parametrize("dim,dtype", [(32, "f32"), (128, "f32"), (256, "bf16"), (1024, "f32")])
+def test_persistent_grid_same_bits(cl, dim, dtype):
+    # a persistent grid only changes which wave runs which work item
+    import torch
+    g = gen.chung_lu(30_000, 250_000, 2.1, 71)  # 175 rows longer than 256 entries
+    ref = cl.embed(g, dim, 3, 9, dtype=dtype)
+    for pack, persistent in [(0, 1), (16, 1), (64, 2), (0, 0)]:
+        with cl.Context(0) as c:
+            c.set_schedule(pack, persistent)
+            c.build_graph(g).init(dim, dtype, 9)
+            sch = c.schedule()
+            assert sch["persistent"] == persistent and sch["split_rows"] > 0
+            if pack:
+                assert sch["pack"] == pack
+            c.propagate(3)
+            assert torch.equal(c.embedding(), ref), (pack, persistent)
+
+
+def test_set_schedule_rejects_bad_values(cl):
+    with cl.Context(0) as c:
+        for pack, persistent in [(8, -1), (1 << 21, -1), (0, 9), (0, -2)]:
+            with pytest.raises(cl.CleoraError):
+                c.set_schedule(pack, persistent)
+
+
 def test_autotune_keeps_results(cl):
     # the packing size only moves rows between waves: same bits before and
     # after tuning, and the tuned choice is reused by later inits
@@ -303,6 +332,8 @@ def test_autotune_keeps_results(cl):
         before = a.embedding().cpu().numpy()
         tuned = a.autotune()
         assert 16 <= tuned["pack"] <= a.schedule()["chunk"]
+        assert a.schedule()["pack"] == tuned["pack"]
+        assert a.schedule()["persistent"] == int(tuned["persistent"])
         assert a.schedule()["packed_items"] > 0
         assert np.array_equal(a.embedding().cpu().numpy(), before)
         assert a.info()["iteration"] == 2
