@@ -41,36 +41,53 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def summarize_trace(trace_dir: str, out: str, command: str) -> None:
+SPMM = "k_spmm_norm"
+
+
+def summarize_trace(trace_dir: str, out: str, last: int, command: str) -> None:
     """Per-kernel summary (calls, average and total duration) of a
-    rocprofv3 --kernel-trace --output-format csv run, as a short text file."""
+    rocprofv3 --kernel-trace --output-format csv run, as a short text file,
+    plus the SpMM kernel over its last `last` dispatches only: the timed
+    steps, after the autotuner's trial launches (0: every dispatch)."""
     import csv
     import glob
     files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
     if not files:
         raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
-    agg = {}
+    agg, spmm = {}, []
     for f in files:
         for r in csv.DictReader(open(f)):
             name = r["Kernel_Name"]
-            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            dur = (t1 - t0) / 1e6
             a = agg.setdefault(name, [0, 0.0])
             a[0] += 1
             a[1] += dur
+            if SPMM in name:
+                spmm.append((t0, dur))
     rows = sorted(agg.items(), key=lambda kv: -kv[1][1])
+    spmm.sort()
+    tail = spmm[-last:] if last > 0 else spmm
     with open(out, "w") as f:
         f.write(f"# rocprofv3 kernel trace summary\n# command: {command}\n")
         f.write(f"# kernel source sha256[:16]: {kernel_source_hash()}\n")
+        if tail:
+            f.write(f"# {SPMM}, last {len(tail)} dispatches (the timed steps): "
+                    f"avg {sum(d for _, d in tail) / len(tail):.4f} ms, "
+                    f"min {min(d for _, d in tail):.4f}, max {max(d for _, d in tail):.4f}\n")
+        f.write("# all dispatches (autotuner trials and warm-up included):\n")
         f.write(f"{'calls':>6} {'avg_ms':>10} {'total_ms':>10}  kernel\n")
         for name, (n, tot) in rows:
             f.write(f"{n:6d} {tot / n:10.4f} {tot:10.3f}  {name[:150]}\n")
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
-                  copy_bytes: int) -> None:
+                  copy_bytes: int, last: int) -> None:
     """HBM-side traffic per launch of the SpMM kernel from two rocprofv3
     --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
-    what the same counter reads for a plain device copy of copy_bytes."""
+    what the same counter reads for a plain device copy of copy_bytes.
+    Only the SpMM kernel's last `last` dispatches count (the timed steps;
+    0: every dispatch)."""
     import csv
     import glob
 
@@ -86,7 +103,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         ref = max(copies) * 1024.0  # the calibration copy is the largest copy
         scale = copy_bytes / ref
-        spmm = [float(r["Counter_Value"]) for r in rows if "k_spmm_norm" in r["Kernel_Name"]]
+        spmm = [float(r["Counter_Value"]) for r in rows if SPMM in r["Kernel_Name"]]
+        if last > 0:
+            spmm = spmm[-last:]
         res[f"{tag}_kib_per_launch_raw"] = sum(spmm) / len(spmm)
         res[f"{tag}_copy_kib_raw"] = ref / 1024.0
         res[f"{tag}_scale"] = scale
@@ -195,12 +214,14 @@ def parse():
 
 
 def main():
+    # summarize-trace TRACE_DIR OUT LAST COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
-        summarize_trace(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        summarize_trace(sys.argv[2], sys.argv[3], int(sys.argv[4]), " ".join(sys.argv[5:]))
         return
+    # summarize-pmc FETCH_DIR WRITE_DIR OUT COPY_BYTES LAST COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-pmc":
-        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[6:]),
-                      int(sys.argv[5]))
+        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[7:]),
+                      int(sys.argv[5]), int(sys.argv[6]))
         return
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
