@@ -252,7 +252,9 @@ def main():
     esz = 2 if dtype == "bf16" else 4
 
     t0 = time.time()
+    gen.graphs.PROGRESS = True  # large graphs take minutes to draw
     g = spec["make"]()
+    gen.graphs.PROGRESS = False
     gen_s = time.time() - t0
     print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", flush=True)
 

@@ -24,9 +24,13 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import time
 from typing import Callable, Optional
 
 import numpy as np
+
+# print one line per drawing round (for long generations)
+PROGRESS = False
 
 BASE_SEED = 2102
 
@@ -64,7 +68,8 @@ def _distinct_pairs(rng: np.random.Generator, n: int, m: int,
         raise ValueError(f"m={m} exceeds the {n * (n - 1) // 2} possible pairs")
     kept = np.empty(0, np.int64)  # sorted, distinct keys lo * n + hi
     gain = 1.0  # distinct pairs gained per pair drawn, from the last round
-    for _ in range(max_rounds):
+    t0 = time.time()
+    for rnd in range(max_rounds):
         deficit = m - kept.size
         if deficit <= 0:
             break
@@ -73,6 +78,9 @@ def _distinct_pairs(rng: np.random.Generator, n: int, m: int,
         b = sampler(k).astype(np.int64)
         ok = a != b
         a, b = a[ok], b[ok]
+        if PROGRESS:
+            print(f"[gen] n={n}: round {rnd}: sampled {k} pairs ({time.time() - t0:.1f}s)",
+                  flush=True)
         new = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
         if kept.size:
             pos = np.searchsorted(kept, new)
@@ -82,6 +90,9 @@ def _distinct_pairs(rng: np.random.Generator, n: int, m: int,
         else:
             kept = new
         gain = max(new.size / k, 1e-3)
+        if PROGRESS:
+            print(f"[gen] n={n}: round {rnd}: drew {k} pairs, {kept.size} of {m} distinct "
+                  f"({time.time() - t0:.1f}s)", flush=True)
     else:
         raise RuntimeError(f"could not draw {m} distinct pairs on {n} nodes")
     if kept.size > m:
