@@ -349,20 +349,43 @@ __global__ __launch_bounds__(256) void k_rowsum_segments(
     }
 }
 
-__global__ __launch_bounds__(256) void k_rowsum_long(
-    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-    const int64_t *__restrict__ seg_base, const double *__restrict__ seg,
-    const int64_t *__restrict__ rp, const double *__restrict__ e_u, float *__restrict__ val,
-    double *__restrict__ deg)
+// deg of each listed row: its segment sums added in segment order.
+__global__ void k_rowsum_long(const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                              const int64_t *__restrict__ seg_base,
+                              const double *__restrict__ seg, double *__restrict__ deg)
 {
     const int cnt = *count;
-    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int64_t r = list[i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x) {
         double d = 0.0;
         for (int64_t q = seg_base[i]; q < seg_base[i + 1]; ++q) d += seg[q];
-        if (threadIdx.x == 0) deg[r] = d;
-        for (int64_t j = rp[r] + threadIdx.x; j < rp[r + 1]; j += blockDim.x)
-            val[j] = (float)(e_u[j] / d);
+        deg[list[i]] = d;
+    }
+}
+
+// M values of the listed rows, one wave per segment (a hub row of 200k
+// entries is spread over 49 waves instead of one block).
+__global__ __launch_bounds__(256) void k_long_values(
+    const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ seg_base, const int64_t *__restrict__ rp,
+    const double *__restrict__ e_u, const double *__restrict__ deg, float *__restrict__ val)
+{
+    const int cnt = *count;
+    const int64_t nseg_total = cnt > 0 ? seg_base[cnt] : 0;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         q < nseg_total; q += (int64_t)gridDim.x * 4) {
+        int lo = 0, hi = cnt - 1;  // the listed row owning segment q
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg_base[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t r = list[lo];
+        const int64_t b = rp[r] + (q - seg_base[lo]) * LONG_ROW;
+        const int64_t e = min(b + (int64_t)LONG_ROW, rp[r + 1]);
+        const double d = deg[r];
+        for (int64_t j = b + lane; j < e; j += 64) val[j] = (float)(e_u[j] / d);
     }
 }
 
@@ -390,9 +413,11 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     if (!directed && n_cols != n) throw Error(CLEORA_E_INVAL, "undirected graphs are square");
     const int64_t total = directed ? m : 2 * m;  // stored entries before merging
     const int64_t tot1 = std::max<int64_t>(total, 1);
-    const int cb = bits_for(n_cols), rb = bits_for(n);
-    const int key_bits = rb + cb + 1;  // row, column, and the bit of the invalid key
-    const uint64_t invalid_key = (uint64_t)1 << (rb + cb);
+    // key = row << cb | col; the invalid key is row n, col 0: above every
+    // valid key, and inside rb = bits(n + 1) row bits, so it costs no pass
+    const int cb = bits_for(n_cols), rb = bits_for(n + 1);
+    const int key_bits = rb + cb;
+    const uint64_t invalid_key = (uint64_t)n << cb;
     const uint64_t cmask = ((uint64_t)1 << cb) - 1;
     const int64_t nblk = ceil_div(tot1, RS_TILE);
 
@@ -485,9 +510,11 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
         k_rowsum_segments<<<1024, 256, 0, s>>>(long_list, long_count, seg_base,
                                                c->rp.as<int64_t>(), esum, seg);
         CLEORA_LAUNCH_CHECK();
-        k_rowsum_long<<<512, 256, 0, s>>>(long_list, long_count, seg_base, seg,
-                                          c->rp.as<int64_t>(), esum, c->val.as<float>(),
-                                          c->deg.as<double>());
+        k_rowsum_long<<<64, 256, 0, s>>>(long_list, long_count, seg_base, seg,
+                                         c->deg.as<double>());
+        CLEORA_LAUNCH_CHECK();
+        k_long_values<<<1024, 256, 0, s>>>(long_list, long_count, seg_base, c->rp.as<int64_t>(),
+                                           esum, c->deg.as<double>(), c->val.as<float>());
         CLEORA_LAUNCH_CHECK();
     }
     CLEORA_HIP(hipMemcpyAsync(c->h_small, small, sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -97,6 +97,25 @@ def test_csr_matches_oracle(cl, gi):
     assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 1023, 1024, 1025, 65536])
+def test_csr_key_width_boundaries(cl, n):
+    # sort keys are row << bits(n_cols) | col with bits(n + 1) row bits: node
+    # counts at and around powers of two, loops (whose second copy is an
+    # invalid key) and repeated pairs
+    for directed in (True, False):
+        g = gen.random_graph(n, 4 * n + 8, 40 + n, directed=directed, weighted=True,
+                             loops=True, multi=True)
+        adj = oracle.build_graph(g)
+        mval, deg = oracle.transition(adj)
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g)
+            csr = {k: v.cpu().numpy() for k, v in ctx.csr().items()}
+        assert np.array_equal(csr["row_ptr"], adj.row_ptr), (n, directed)
+        assert np.array_equal(csr["col"], adj.col), (n, directed)
+        assert np.allclose(csr["deg"], deg, rtol=1e-15, atol=0)
+        assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001)
+
+
 def test_csr_long_rows_weighted(cl):
     # one row of 40k entries (block radix sort), rows of ~5k (LDS sort),
     # repeated weighted pairs to merge
