@@ -157,6 +157,18 @@ def served_main(args) -> dict:
     base = latency_stats(one_at_a_time(jobs(1.0 / rate), dim, k, "f32", result_on_device=True),
                          k, dim, nnz_of)
     base["dtype"] = "f32"
+    other_loads = []
+    for ld in [float(x) for x in args.loads.split(",") if x]:
+        r = ld * cap["req_per_s"]
+        st = latency_stats(run_native(jobs(1.0 / r), dim, args.served_dtype, k, **opts),
+                           k, dim, nnz_of)
+        row = {"load": ld, "offered_req_per_s": round(r, 2),
+               "continuous_batching": {key: st[key] for key in ("p50_ms", "p99_ms", "req_per_s")}}
+        st = latency_stats(one_at_a_time(jobs(1.0 / r), dim, k, "f32", result_on_device=True),
+                           k, dim, nnz_of)
+        row["one_at_a_time_f32"] = {key: st[key] for key in ("p50_ms", "p99_ms", "req_per_s")}
+        print(f"[served] load {ld}: {row}", flush=True)
+        other_loads.append(row)
     sweep = []
     for r in [float(x) for x in args.rates.split(",") if x]:
         row = {"offered_req_per_s": r}
@@ -175,6 +187,8 @@ def served_main(args) -> dict:
            "max_group": args.max_group,
            "saturated_capacity": cap, "continuous_batching": batched,
            "one_at_a_time_f32": base}
+    if other_loads:
+        out["other_loads"] = other_loads
     if sweep:
         out["rate_sweep"] = sweep
     return out
@@ -204,6 +218,9 @@ def parse():
     ap.add_argument("--max-group", type=int, default=16,
                     help="most requests the server builds together as one block-diagonal graph")
     ap.add_argument("--served-dtype", default="bf16")
+    ap.add_argument("--loads", default="0.5,0.9",
+                    help="further offered loads (multiples of the measured capacity) to report "
+                         "beside --load")
     ap.add_argument("--rates", default="",
                     help="comma-separated offered rates (req/s): latency at each, grouped and "
                          "ungrouped, beside one-at-a-time FP32")
@@ -381,6 +398,8 @@ def _traffic(workload: str, dtype: str):
 def _cpu_baseline(g, dim: int, k: int) -> dict:
     """The FP64 oracle on the host cores: the same whole path (adjacency,
     M, T_0, k iterations) on the same graph, timed once."""
+    import numpy as np
+
     import oracle
     threads = oracle.get_threads()
     t0 = time.perf_counter()
@@ -389,10 +408,35 @@ def _cpu_baseline(g, dim: int, k: int) -> dict:
     T0 = oracle.init(2102, g.n, dim)
     oracle.propagate(adj, mval, T0, k)
     dt = time.perf_counter() - t0
+    # one thread: one iteration over the first N/16 rows (propagation only)
+    T1 = np.empty_like(T0)
+    r1 = max(1, g.n // 16)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.step_rows(adj, mval, T0, T1, 0, r1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    ed1 = int(adj.row_ptr[r1]) * dim
     return {"value": round(k * adj.nnz * dim / dt / 1e9, 4), "unit": "GEdge-dims/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"whole path on the full graph (n={g.n}, nnz={adj.nnz}, d={dim}, k={k}), "
-                      f"FP64, {dt:.1f}s"}
+                      f"FP64, {dt:.1f}s",
+            "single_thread": {"value": round(ed1 / dt1 / 1e9, 4), "unit": "GEdge-dims/s",
+                              "sample": f"one FP64 iteration over rows [0, {r1}), "
+                                        f"propagation only, {dt1:.1f}s"}}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":
