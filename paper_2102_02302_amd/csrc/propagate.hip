@@ -248,11 +248,11 @@ __device__ __forceinline__ void gather_rows(float (&acc)[VPL][EmbT<T>::EPV], int
                 for (int e = 0; e < EPV; ++e) acc[v][e] = fmaf(w[u], f[e], acc[v][e]);
             }
     }
-    for (; j < je; j += G) {
-        const int64_t jj = j + grp;
-        if (jj < je) {
-            const int32_t c = col[jj];
-            const float w = val[jj];
+    if constexpr (G == 1) {
+        // one row per wave: other waves hide the latency of a short tail
+        for (; j < je; ++j) {
+            const int32_t c = col[j];
+            const float w = val[j];
             const uint4 *row = Ein + (int64_t)c * vrow;
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
@@ -265,6 +265,41 @@ __device__ __forceinline__ void gather_rows(float (&acc)[VPL][EmbT<T>::EPV], int
                 }
             }
         }
+    } else if (j < je) {
+        // narrow rows, G per wave: the last < G*U entries in one predicated
+        // round, all loads in flight together; each group still adds its
+        // entries in ascending order
+        int32_t c[U];
+        float w[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t jj = j + u * G + grp;
+            ok[u] = jj < je;
+            const int64_t js = ok[u] ? jj : je - 1;  // an in-range index for the unused slots
+            c[u] = col[js];
+            w[u] = val[js];
+        }
+        uint4 x[U][VPL];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint4 *row = Ein + (int64_t)c[u] * vrow;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                const int ch = gl + v * LPG;
+                x[u][v] = (ok[u] && ch < cpr) ? row[ch] : make_uint4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                float f[EPV];
+                widen<T>(x[u][v], f);
+#pragma unroll
+                for (int e = 0; e < EPV; ++e)
+                    acc[v][e] = ok[u] ? fmaf(w[u], f[e], acc[v][e]) : acc[v][e];
+            }
     }
 }
 
