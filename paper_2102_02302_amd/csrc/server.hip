@@ -292,6 +292,12 @@ struct cleora_server {
             g->status = status;
             const double t = seconds_since(t0);
             for (SReq *q : g->members) q->ready_s = t;
+            if (stop) {
+                // nobody steps it any more (destroy, or a device error)
+                if (g->status == CLEORA_OK) g->status = CLEORA_E_DEVICE;
+                finish(g);
+                continue;
+            }
             ready.push_back(g);
             cv_sched.notify_one();
             cv_build.notify_one();
@@ -414,6 +420,9 @@ struct cleora_server {
                 }
                 active.swap(still);
             } catch (const std::exception &e) {
+                // the server stops: every request not yet completed
+                // completes now with E_DEVICE (groups still building do so
+                // when their builder returns)
                 std::lock_guard<std::mutex> lk(mu);
                 fatal = e.what();
                 for (Group *g : active) {
@@ -422,12 +431,26 @@ struct cleora_server {
                 }
                 active.clear();
                 for (auto &p : retiring) {
+                    ev_pool.push_back(p.first);
                     p.second->status = CLEORA_E_DEVICE;
                     finish(p.second);
                 }
                 retiring.clear();
+                for (Group *g : ready) {
+                    g->status = CLEORA_E_DEVICE;
+                    finish(g);
+                }
+                ready.clear();
+                const double t = seconds_since(t0);
+                for (SReq *q : pending) {
+                    q->status = CLEORA_E_DEVICE;
+                    q->done_s = t;
+                    done.push_back(q);
+                }
+                pending.clear();
                 stop = true;
                 cv_build.notify_all();
+                cv_done.notify_all();
                 return;
             }
         }
