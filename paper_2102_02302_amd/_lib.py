@@ -69,6 +69,10 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2102_02302_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch loaded.
+    # Loaded the other way round, torch could not initialise its GPU
+    # afterwards in the same process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     p, i32, i64, u32, u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                              ctypes.c_uint64)

@@ -289,11 +289,21 @@ def latency_stats(done: Sequence[Job], k: int, dim: int, nnz_of: Callable[[Job],
     lat = np.array([j.latency_s for j in done]) * 1e3
     span = max(j.done_s for j in done) - min(j.arrival_s for j in done)
     edge_dims = sum(nnz_of(j) for j in done) * float(k) * dim
-    return {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
-            "req_per_s": round(len(done) / span, 2),
-            "gedge_dims_per_s": round(edge_dims / span / 1e9, 3), "span_s": round(span, 3)}
+    out = {"requests": len(done), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3), "max_ms": round(float(lat.max()), 3),
+           "req_per_s": round(len(done) / span, 2),
+           "gedge_dims_per_s": round(edge_dims / span / 1e9, 3), "span_s": round(span, 3)}
+    if all(j.admitted_s >= 0 and j.ready_s >= 0 for j in done):
+        # where the time goes: waiting for admission, build + init, k steps
+        # and the copy of the result
+        phases = {"queue": [j.admitted_s - j.arrival_s for j in done],
+                  "build": [j.ready_s - j.admitted_s for j in done],
+                  "steps": [j.done_s - j.ready_s for j in done]}
+        out["phases_ms"] = {name: {"p50": round(float(np.percentile(v, 50)) * 1e3, 3),
+                                   "p99": round(float(np.percentile(v, 99)) * 1e3, 3)}
+                            for name, v in phases.items()}
+    return out
 
 
 class NativeServer:
@@ -301,7 +311,7 @@ class NativeServer:
     policy as ``Scheduler``, with native scheduler and builder threads."""
 
     def __init__(self, dim: int, dtype: str, k: int, slots: int = 64,
-                 budget_bytes: int = 64 << 30, builders: int = 4, device: int = 0,
+                 budget_bytes: int = 64 << 30, builders: int = 3, device: int = 0,
                  directed: bool = False, max_group: int = 16):
         from . import DIRECTED, _dtype_code, _lib
         self._lib = _lib.load()
@@ -369,7 +379,7 @@ class NativeServer:
 
 
 def run_native(jobs: Sequence[Job], dim: int, dtype: str, k: int, slots: int = 64,
-               budget_bytes: int = 64 << 30, builders: int = 4, device: int = 0,
+               budget_bytes: int = 64 << 30, builders: int = 3, device: int = 0,
                keep_results: bool = False, server: Optional[NativeServer] = None,
                max_group: int = 16) -> List[Job]:
     """Serve ``jobs`` (arrival times in seconds from the start) with the
@@ -394,6 +404,7 @@ def run_native(jobs: Sequence[Job], dim: int, dtype: str, k: int, slots: int = 6
     torch.cuda.synchronize()
     by_ticket, done = {}, []
     try:
+        s0 = srv.stats()
         t0 = srv.now()
 
         def drain(wait):
@@ -417,7 +428,12 @@ def run_native(jobs: Sequence[Job], dim: int, dtype: str, k: int, slots: int = 6
             by_ticket[srv.submit(j.payload.n, src, dst, w, j.seed, outs[j.index])] = j
         while by_ticket:
             drain(0.05)
-        run_native.last_stats = srv.stats()
+        # counters of this run (a long-lived server accumulates them); the
+        # maxima are over the server's life
+        st = srv.stats()
+        for key in ("steps", "request_steps", "groups"):
+            st[key] -= s0[key]
+        run_native.last_stats = st
     finally:
         if own:
             srv.close()

@@ -129,3 +129,32 @@ def test_native_server_reports_bad_requests(cl, max_group):
             srv.submit(0, good.src, good.dst, None, 1, outs[0])
     finally:
         srv.close()
+
+
+def test_server_before_torch_in_fresh_process(cl):
+    """A process whose first GPU user is the library (a server created
+    before anything touches torch.cuda) can still allocate torch tensors."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "from paper_2102_02302_amd.serve import NativeServer\n"
+        "import numpy as np\n"
+        "srv = NativeServer(16, 'f32', 2, slots=2, budget_bytes=1 << 28, builders=1)\n"
+        "import torch\n"
+        "out = torch.empty((3, 16), device='cuda')\n"
+        "src = np.array([0, 1], np.int32); dst = np.array([1, 2], np.int32)\n"
+        "t = srv.submit(3, src, dst, None, 5, out)\n"
+        "got = []\n"
+        "while not got:\n"
+        "    got = srv.poll(4, 1.0)\n"
+        "assert got[0][0] == t and got[0][1] == 0, got\n"
+        "import paper_2102_02302_amd as cl, gen\n"
+        "g = gen.Graph(3, src, dst, None, False)\n"
+        "assert torch.equal(out, cl.embed(g, 16, 2, 5))\n"
+        "srv.close()\n"
+        "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
