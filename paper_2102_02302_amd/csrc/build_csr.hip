@@ -28,7 +28,7 @@ namespace {
 constexpr uint32_t ERR_ID = 1u, ERR_WEIGHT = 2u;
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 8;
+constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block and pass
 constexpr int LONG_ROW = 4096;                  // rows summed in segments
 
@@ -112,33 +112,43 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     count[(int64_t)t * nblk + blockIdx.x] = (int32_t)s;
 }
 
-// Radix pass, step 3: stable scatter.  Keys of the tile are ranked in input
-// order (rounds of 256; within a round by wave, then lane), staged in LDS in
-// digit order, and written out run by run.
+// Radix pass, step 3: stable scatter.  Wave w ranks the tile's keys
+// [w*512, (w+1)*512) in rounds of 64 (by round, then lane), keeping running
+// per-digit counts in its own LDS row, so ranking needs no block barrier;
+// one per-digit prefix over the waves then gives every key its place in
+// the tile in input order.  Keys are staged in LDS in digit order and
+// written out run by run.
 template <bool PAYLOAD>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const float *__restrict__ pin, int64_t n, int shift,
     int64_t nblk, const int64_t *__restrict__ offs, uint64_t *__restrict__ kout,
     float *__restrict__ pout)
 {
+    constexpr int NW = RS_THREADS / WAVE;  // waves per block
+    constexpr int CHUNK = RS_TILE / NW;    // keys per wave
+    static_assert(RS_THREADS == 256, "one thread per digit");
     __shared__ uint64_t sk[RS_TILE];
     __shared__ float sp[PAYLOAD ? RS_TILE : 1];
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[NW][256];  // per-wave digit counts, then per-wave digit starts
+    __shared__ uint32_t total[256];
     __shared__ uint32_t dstart[256];
-    __shared__ uint16_t wc[RS_THREADS / WAVE][256];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    run[t] = 0;
+    const int64_t wbase = base + (int64_t)w * CHUNK;
     uint64_t key[RS_ITEMS];
+    float pay[PAYLOAD ? RS_ITEMS : 1];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = wbase + i * WAVE + lane;
+        key[i] = idx < n ? kin[idx] : 0;
+        if constexpr (PAYLOAD) pay[i] = idx < n ? pin[idx] : 0.0f;
+    }
+    for (int q = lane; q < 256; q += WAVE) wc[w][q] = 0;
     uint32_t rank[RS_ITEMS];
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
-        const int64_t idx = base + i * RS_THREADS + t;
-        const bool valid = idx < n;
-        key[i] = valid ? kin[idx] : 0;
+        const bool valid = wbase + i * WAVE + lane < n;
         const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
-        for (int q = t; q < (RS_THREADS / WAVE) * 256; q += RS_THREADS) (&wc[0][0])[q] = 0;
-        __syncthreads();
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -146,28 +156,36 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
             const uint64_t mk = __ballot(bit);
             peers &= bit ? mk : ~mk;
         }
-        const uint32_t inwave = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-        if (valid && inwave == 0) wc[w][d] = (uint16_t)__popcll(peers);
-        __syncthreads();
-        {
-            uint32_t s = run[t];
-            for (int q = 0; q < RS_THREADS / WAVE; ++q) {
-                const uint32_t c = wc[q][t];
-                wc[q][t] = (uint16_t)s;
-                s += c;
-            }
-            run[t] = s;
-        }
-        __syncthreads();
-        rank[i] = valid ? (uint32_t)wc[w][d] + inwave : 0xffffffffu;
-        __syncthreads();
+        const uint32_t below = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+        // the wave's own row: earlier writes by other lanes of this wave
+        // must be seen, later ones must not be read early
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t before = wc[w][d];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) wc[w][d] = before + (uint32_t)__popcll(peers);
+        rank[i] = valid ? before + below : 0xffffffffu;
     }
-    // local digit starts: exclusive scan of run[] (256 entries, one wave)
+    __syncthreads();
+    {
+        // digit t: exclusive prefix over the waves
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            const uint32_t c = wc[q][t];
+            wc[q][t] = s;
+            s += c;
+        }
+        total[t] = s;
+    }
+    __syncthreads();
+    // local digit starts: exclusive scan of total[] (256 entries, one wave)
     if (w == 0) {
         uint32_t v[4], tot = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            v[q] = run[lane * 4 + q];
+            v[q] = total[lane * 4 + q];
             tot += v[q];
         }
         uint32_t x = tot;
@@ -187,9 +205,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     for (int i = 0; i < RS_ITEMS; ++i) {
         if (rank[i] == 0xffffffffu) continue;
         const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
-        const uint32_t lp = dstart[d] + rank[i];
+        const uint32_t lp = dstart[d] + wc[w][d] + rank[i];
         sk[lp] = key[i];
-        if constexpr (PAYLOAD) sp[lp] = pin[base + i * RS_THREADS + t];
+        if constexpr (PAYLOAD) sp[lp] = pay[i];
     }
     __syncthreads();
     const int64_t cnt = min((int64_t)RS_TILE, n - base);
@@ -278,8 +296,12 @@ __global__ void k_row_counts(int64_t n, const unsigned long long *__restrict__ n
     }
 }
 
-// deg(a) and M values; rows longer than LONG_ROW are listed for the block
-// kernel.  Per-lane partial sums are combined in a fixed butterfly order.
+// deg(a) and M values, four rows per wave.  When all four rows hold at most
+// 16 (32) entries they are summed by 16- (32-) lane groups: a 64-lane
+// butterfly over a row that short only adds exact zeros in its first
+// steps, so the grouping gives the same bits.  Otherwise the rows take one
+// 64-lane pass each; rows longer than LONG_ROW are listed for the
+// segmented kernels.
 __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *__restrict__ rp,
                                                      const double *__restrict__ e_u,
                                                      float *__restrict__ val,
@@ -287,19 +309,41 @@ __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *_
                                                      int32_t *__restrict__ long_list,
                                                      int32_t *__restrict__ long_count)
 {
-    const int64_t row = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (row >= n) return;
+    const int64_t r0 =
+        ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * 4;
+    if (r0 >= n) return;
     const int lane = threadIdx.x & 63;
-    const int64_t lo = rp[row], hi = rp[row + 1];
-    if (hi - lo > LONG_ROW) {
-        if (lane == 0) long_list[atomicAdd(long_count, 1)] = (int32_t)row;
+    const int nr = (int)min((int64_t)4, n - r0);
+    int64_t maxlen = 0;
+    for (int q = 0; q < nr; ++q) maxlen = max(maxlen, rp[r0 + q + 1] - rp[r0 + q]);
+    if (maxlen <= 32) {
+        const int width = maxlen <= 16 ? 16 : 32, per = 64 / width;
+        const int q = lane / width, gl = lane % width;
+        for (int base = 0; base < nr; base += per) {
+            const int64_t row = r0 + base + q;
+            const bool in = base + q < nr;
+            const int64_t lo = in ? rp[row] : 0, hi = in ? rp[row + 1] : 0;
+            const bool has = lo + gl < hi;
+            const double e = has ? e_u[lo + gl] : 0.0;
+            const double s = width == 16 ? group_sum<16>(e) : group_sum<32>(e);
+            if (in && gl == 0) deg[row] = s;
+            if (has) val[lo + gl] = (float)(e / s);
+        }
         return;
     }
-    double s = 0.0;
-    for (int64_t j = lo + lane; j < hi; j += 64) s += e_u[j];
-    s = wave_sum(s);
-    if (lane == 0) deg[row] = s;
-    for (int64_t j = lo + lane; j < hi; j += 64) val[j] = (float)(e_u[j] / s);
+    for (int q = 0; q < nr; ++q) {
+        const int64_t row = r0 + q;
+        const int64_t lo = rp[row], hi = rp[row + 1];
+        if (hi - lo > LONG_ROW) {
+            if (lane == 0) long_list[atomicAdd(long_count, 1)] = (int32_t)row;
+            continue;
+        }
+        double s = 0.0;
+        for (int64_t j = lo + lane; j < hi; j += 64) s += e_u[j];
+        s = wave_sum(s);
+        if (lane == 0) deg[row] = s;
+        for (int64_t j = lo + lane; j < hi; j += 64) val[j] = (float)(e_u[j] / s);
+    }
 }
 
 // Long rows: segment q of a listed row (LONG_ROW entries each) is summed by
@@ -494,7 +538,7 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     CLEORA_LAUNCH_CHECK();
     // deg(a) and M values
     int32_t *long_list = count;  // the digit counts are no longer needed
-    k_rowsum_wave<<<(unsigned)ceil_div(n, 4), 256, 0, s>>>(n, c->rp.as<int64_t>(), esum,
+    k_rowsum_wave<<<(unsigned)ceil_div(n, 16), 256, 0, s>>>(n, c->rp.as<int64_t>(), esum,
                                                            c->val.as<float>(), c->deg.as<double>(),
                                                            long_list, long_count);
     CLEORA_LAUNCH_CHECK();
