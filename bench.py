@@ -246,6 +246,8 @@ def parse():
     ap.add_argument("--rates", default="",
                     help="comma-separated offered rates (req/s): latency at each, grouped and "
                          "ungrouped, beside one-at-a-time FP32")
+    ap.add_argument("--graph-cache", default="",
+                    help="directory to keep drawn workload graphs in (reused by later runs)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="launch one plain device copy of this many GiB first "
                          "(reference kernel for HBM counter scaling)")
@@ -291,9 +293,7 @@ def main():
     esz = 2 if dtype == "bf16" else 4
 
     t0 = time.time()
-    gen.graphs.PROGRESS = True  # large graphs take minutes to draw
-    g = spec["make"]()
-    gen.graphs.PROGRESS = False
+    g = _cached_graph(args.graph_cache, args.workload, spec)
     gen_s = time.time() - t0
     print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", flush=True)
 
@@ -415,6 +415,29 @@ def _traffic(workload: str, dtype: str):
     if s.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return s.get("hbm_bytes_per_launch")
+
+
+def _cached_graph(cache_dir: str, name: str, spec: dict):
+    """The workload's seeded graph; with a cache directory, drawn once and
+    then loaded from DIR/<name>.npz (the draw is deterministic)."""
+    import numpy as np
+
+    import gen
+    path = os.path.join(cache_dir, f"{name}.npz") if cache_dir else ""
+    if path and os.path.exists(path):
+        z = np.load(path)
+        w = z["w"] if z["w"].size else None
+        return gen.Graph(int(z["n"]), z["src"], z["dst"], w, bool(z["directed"]), name)
+    gen.graphs.PROGRESS = True  # large graphs take minutes to draw
+    try:
+        g = spec["make"]()
+    finally:
+        gen.graphs.PROGRESS = False
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(path, n=g.n, src=g.src, dst=g.dst, directed=g.directed,
+                 w=g.w if g.w is not None else np.zeros(0, np.float32))
+    return g
 
 
 def _cpu_baseline(g, dim: int, k: int) -> dict:
