@@ -168,7 +168,11 @@ def test_bipartite6m_vs_oracle(cl):
 @pytest.mark.timeout(1200)
 def test_chunglu10m_sampled(cl):
     import torch
-    g, dim, k, _ = gen.workload("chunglu10m")
+    gen.graphs.PROGRESS = True  # a few minutes of drawing: say so as it goes
+    try:
+        g, dim, k, _ = gen.workload("chunglu10m")
+    finally:
+        gen.graphs.PROGRESS = False
     rows, deg = sample_rows(g, 1000, 2)
     want1 = oracle.t1_rows(g, rows, dim, 9)
     idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
