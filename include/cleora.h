@@ -100,6 +100,16 @@ int cleora_build_csr(cleora_ctx *ctx, int64_t n_nodes, int64_t n_edges, const in
  * dtype), E_NOMEM, E_DEVICE. */
 int cleora_init(cleora_ctx *ctx, int32_t dim, int32_t dtype, uint64_t seed, void *stream);
 
+/* cleora_build_csr + cleora_init in one call (Section 3.2: M, then T_0),
+ * with T_0 written on an internal stream while the CSR is built on
+ * `stream` (T_0 depends only on n_nodes, dim and the seed).  `stream`
+ * waits for both before any later work on it.  Arguments, results and
+ * errors as the two calls; on failure no embedding is left (E_STATE for
+ * cleora_propagate until the next successful build and init). */
+int cleora_build_init(cleora_ctx *ctx, int64_t n_nodes, int64_t n_edges, const int32_t *src,
+                      const int32_t *dst, const float *w, uint32_t flags, int32_t dim,
+                      int32_t dtype, uint64_t seed, void *stream);
+
 /* Run k more iterations of Algorithm 1 (multiply by M, then L2-normalise
  * each row; a row whose product is exactly zero becomes zero, see
  * CLEORA_EMPTY_KEEP).  k = 0 does nothing.  Calls continue from the current

@@ -119,6 +119,27 @@ class Context:
         """Build from a ``gen.Graph``-like object (n, src, dst, w, directed)."""
         return self.build_csr(g.n, g.src, g.dst, g.w, g.directed, empty_keep, stream)
 
+    def build_init(self, n_nodes: int, src, dst, w=None, dim: int = 128, dtype="f32",
+                   seed: int = 0, directed: bool = False, empty_keep: bool = False,
+                   stream=None) -> "Context":
+        """build_csr + init in one call, T_0 written while the CSR is built."""
+        s = _dev_i32(src, self.device)
+        d = _dev_i32(dst, self.device)
+        wt = _dev_f32(w, self.device)
+        flags = (DIRECTED if directed else 0) | (EMPTY_KEEP if empty_keep else 0)
+        _lib.check(self._lib.cleora_build_init(self._h, int(n_nodes), int(s.numel()), _ptr(s),
+                                               _ptr(d), _ptr(wt), flags, int(dim),
+                                               _dtype_code(dtype), int(seed) & (2**64 - 1),
+                                               _stream(stream)))
+        self._keep = [s, d, wt]
+        return self
+
+    def build_graph_init(self, g, dim: int, dtype="f32", seed: int = 0,
+                         empty_keep: bool = False, stream=None) -> "Context":
+        """build_init from a ``gen.Graph``-like object."""
+        return self.build_init(g.n, g.src, g.dst, g.w, dim, dtype, seed, g.directed, empty_keep,
+                               stream)
+
     def set_chunk(self, chunk: int) -> None:
         _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
 
@@ -282,10 +303,9 @@ def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
           empty_keep: bool = False, chunk: int = 0):
     """Whole path for one graph: build M, initialise T_0, k iterations."""
     with Context(device) as ctx:
-        ctx.build_graph(g, empty_keep=empty_keep)
         if chunk:
             ctx.set_chunk(chunk)
-        ctx.init(dim, dtype, seed)
+        ctx.build_graph_init(g, dim, dtype, seed, empty_keep=empty_keep)
         ctx.propagate(k)
         return ctx.embedding()
 

@@ -23,6 +23,7 @@ _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
 
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
+    "cleora_build_init",
     "cleora_init", "cleora_propagate", "cleora_get_embedding", "cleora_embedding_ptr",
     "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
     "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
@@ -81,6 +82,7 @@ def load() -> ctypes.CDLL:
         "cleora_destroy": (None, [p]),
         "cleora_footprint_bytes": (ctypes.c_size_t, [i64, i64, u32, i32, i32]),
         "cleora_build_csr": (ctypes.c_int, [p, i64, i64, p, p, p, u32, p]),
+        "cleora_build_init": (ctypes.c_int, [p, i64, i64, p, p, p, u32, i32, i32, u64, p]),
         "cleora_init": (ctypes.c_int, [p, i32, i32, u64, p]),
         "cleora_propagate": (ctypes.c_int, [p, i32, p]),
         "cleora_get_embedding": (ctypes.c_int, [p, p, i64, i32, p]),

@@ -70,9 +70,11 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
 // T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and
 // local indices), or a single graph when n_graphs == 1 and row0 == nullptr.
 // With ids != nullptr, row i uses global index ids[i] (chunks of a graph).
+// max_blocks caps the grid (0: as many blocks as the work allows), so that
+// the init can run beside other work instead of filling every CU.
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
                  const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
-                 const int32_t *ids = nullptr);
+                 const int32_t *ids = nullptr, int64_t max_blocks = 0);
 
 // Hypergraph expansion (expand.hip).  expand_clique returns the edge count
 // (and writes nothing when src is null).
@@ -129,6 +131,9 @@ struct cleora_ctx {
     // captured k-iteration graphs, keyed by (k, starting parity)
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;
+    // side stream of cleora_build_init (T_0 written during the build)
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // timing
     bool timing = false;
@@ -154,9 +159,6 @@ int32_t tuned_persist(const cleora_ctx *c);
 void write_descs(cleora_ctx *c, hipStream_t s);
 StepDesc host_desc(const cleora_ctx *c, int parity);
 // runtime.hip helpers shared with the server
-void build_and_init(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                    const float *w, uint32_t flags, int32_t dim, int32_t dtype, uint64_t seed,
-                    hipStream_t s);
 void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s);
 // Several graphs as one block-diagonal graph: their edges concatenated in
 // device memory (local ids, rewritten in place), graph g owning edges

@@ -683,11 +683,11 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
 
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
                  const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
-                 const int32_t *ids)
+                 const int32_t *ids, int64_t max_blocks)
 {
     const int epv = dtype == CLEORA_BF16 ? 8 : 4;
     const int64_t total = n * (ld / epv);
-    const unsigned g = grid_for(total, 256, 1 << 16);
+    const unsigned g = grid_for(total, 256, max_blocks > 0 ? max_blocks : 1 << 16);
     if (dtype == CLEORA_BF16)
         k_init<uint16_t><<<g, 256, 0, s>>>(reinterpret_cast<uint16_t *>(E), n, dim, ld, row0,
                                            seeds, n_graphs, seed0, ids);

@@ -1,9 +1,11 @@
 // C ABI of the library: contexts, argument checks, launches, errors.
 // Every entry point catches everything and returns a CLEORA_* status.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -175,7 +177,18 @@ void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
     c->iteration += k;
 }
 
-void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
+int device_cus(int device)
+{
+    static std::atomic<int> cached[64] = {};
+    if (device >= 0 && device < 64 && cached[device].load() > 0) return cached[device].load();
+    int cus = 0;
+    CLEORA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    if (device >= 0 && device < 64) cached[device].store(cus);
+    return cus;
+}
+
+// The two embedding buffers for n rows (the schedule comes later).
+void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
 {
     drop_graphs(c);
     c->has_emb = false;
@@ -183,14 +196,55 @@ void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
     c->chunk = c->chunk_req > 0 ? c->chunk_req : default_split(c->ld, dtype);
-    const size_t ebytes = (size_t)c->n * (size_t)c->ld * elem_size(dtype);
+    const size_t ebytes = (size_t)n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
+}
+
+// The propagation schedule of the current graph and embedding layout.
+void plan_embedding(cleora_ctx *c, hipStream_t s)
+{
     cleora::plan_schedule(c, s);
     c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
     cleora::write_descs(c, s);
     c->cur = 0;
     c->iteration = 0;
+}
+
+void setup_embedding(cleora_ctx *c, int32_t dim, int32_t dtype, hipStream_t s)
+{
+    alloc_embedding(c, c->n, dim, dtype);
+    plan_embedding(c, s);
+}
+
+// Build the CSR on s while T_0 is written on the context's side stream:
+// T_0 needs only N, d and the seed, so the ALU-bound init overlaps the
+// memory-bound build.  s waits for the init before the call returns (also
+// when the build fails, so that E is not released under it).
+void build_overlapping_init(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype, hipStream_t s,
+                            const std::function<void()> &build,
+                            const std::function<void(hipStream_t)> &init)
+{
+    alloc_embedding(c, n, dim, dtype);
+    if (!c->side_stream) {
+        CLEORA_HIP(hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking));
+        CLEORA_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        CLEORA_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    // earlier work on s may still read E
+    CLEORA_HIP(hipEventRecord(c->ev_fork, s));
+    CLEORA_HIP(hipStreamWaitEvent(c->side_stream, c->ev_fork, 0));
+    init(c->side_stream);
+    CLEORA_HIP(hipEventRecord(c->ev_join, c->side_stream));
+    try {
+        build();
+        plan_embedding(c, s);
+    } catch (...) {
+        (void)hipStreamWaitEvent(s, c->ev_join, 0);
+        throw;
+    }
+    CLEORA_HIP(hipStreamWaitEvent(s, c->ev_join, 0));
+    c->has_emb = true;
 }
 
 __global__ void k_offset_edges(int64_t m, const int32_t *__restrict__ src,
@@ -227,22 +281,6 @@ int32_t tuned_persist(const cleora_ctx *c)
 }  // namespace cleora
 
 namespace cleora {
-
-// Build + T_0 for one context from device edge arrays (the served form's
-// builder threads call this on their own streams).
-void build_and_init(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
-                    const float *w, uint32_t flags, int32_t dim, int32_t dtype, uint64_t seed,
-                    hipStream_t s)
-{
-    check_graph_sizes(n, m);
-    check_dim(dim, dtype);
-    drop_graphs(c);
-    c->is_chunk = false;
-    build_graph(c, n, n, m, src, dst, w, flags, s);
-    setup_embedding(c, dim, dtype, s);
-    launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s);
-    c->has_emb = true;
-}
 
 // One iteration for each context in one set of launches; synchronises s.
 void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s)
@@ -366,6 +404,9 @@ void cleora_destroy(cleora_ctx *c)
                           &c->t_scan, &c->t_small, &c->multi_desc};
         drop_graphs(c);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
+        if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+        if (c->ev_join) (void)hipEventDestroy(c->ev_join);
         for (DevBuf *b : bufs) b->release();
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->h_small) (void)hipHostFree(c->h_small);
@@ -421,6 +462,31 @@ int cleora_init(cleora_ctx *c, int32_t dim, int32_t dtype, uint64_t seed, void *
     cleora::launch_init(dtype, c->E[0].p, c->n, dim, c->ld, nullptr, nullptr, 1, seed, s,
                         c->is_chunk ? c->chunk_ids.as<int32_t>() : nullptr);
     c->has_emb = true;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_build_init(cleora_ctx *c, int64_t n_nodes, int64_t n_edges, const int32_t *src,
+                      const int32_t *dst, const float *w, uint32_t flags, int32_t dim,
+                      int32_t dtype, uint64_t seed, void *stream)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    check_graph_sizes(n_nodes, n_edges);
+    if (n_edges > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst NULL");
+    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "bad flags");
+    check_dim(dim, dtype);
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    c->is_chunk = false;
+    build_overlapping_init(
+        c, n_nodes, dim, dtype, s,
+        [&] { cleora::build_graph(c, n_nodes, n_nodes, n_edges, src, dst, w, flags, s); },
+        [&](hipStream_t side) {
+            // two blocks per CU: the init shares the CUs with the build
+            cleora::launch_init(dtype, c->E[0].p, n_nodes, dim, c->ld, nullptr, nullptr, 1, seed,
+                                side, nullptr, 2 * (int64_t)device_cus(c->device));
+        });
     return CLEORA_OK;
     ABI_END
 }

@@ -361,3 +361,36 @@ def test_autotune_keeps_results(cl):
     with cl.Context(0) as b:
         b.build_graph(g).init(128, "f32", 4).propagate(4)
         assert np.array_equal(b.embedding().cpu().numpy(), after)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_build_init_equals_separate_calls(cl, dtype):
+    import torch
+    for g in (gen.chung_lu(20_000, 150_000, 2.1, 81),
+              gen.random_graph(3000, 9000, 82, directed=True, weighted=True, loops=True,
+                               multi=True)):
+        with cl.Context(0) as a, cl.Context(0) as b:
+            a.build_graph(g).init(96, dtype, 5).propagate(3)
+            b.build_graph_init(g, 96, dtype, 5).propagate(3)
+            assert torch.equal(a.embedding(), b.embedding()), g.name
+            # k = 0 returns T_0 itself
+            b.build_graph_init(g, 96, dtype, 6)
+            a.init(96, dtype, 6)
+            assert torch.equal(a.embedding(), b.embedding()), g.name
+
+
+def test_build_init_bad_input_leaves_no_embedding(cl):
+    g = gen.erdos_renyi(500, 2000, 83)
+    bad = g.dst.copy()
+    bad[10] = 500
+    with cl.Context(0) as c:
+        c.build_graph_init(g, 32, "f32", 1).propagate(1)
+        with pytest.raises(cl.CleoraError) as e:
+            c.build_init(g.n, g.src, bad, None, 32, "f32", 1)
+        assert "E_INPUT" in str(e.value)
+        with pytest.raises(cl.CleoraError):
+            c.propagate(1)
+        c.build_graph_init(g, 32, "f32", 1).propagate(2)
+        want = cl.embed(g, 32, 2, 1)
+        import torch
+        assert torch.equal(c.embedding(), want)
