@@ -158,3 +158,42 @@ def test_server_before_torch_in_fresh_process(cl):
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+def test_native_server_concurrent_submitters(cl):
+    """Four threads submit at once (ctypes releases the GIL in the calls);
+    every ticket completes once, with its solo result."""
+    import threading
+
+    import torch
+    from paper_2102_02302_amd.serve import NativeServer
+    graphs = [gen.erdos_renyi(200 + 37 * i, 900 + 101 * i, 90 + i) for i in range(24)]
+    outs = [torch.empty((g.n, 32), device="cuda") for g in graphs]
+    torch.cuda.synchronize()
+    srv = NativeServer(32, "f32", 3, slots=4, budget_bytes=1 << 30, builders=3, max_group=4)
+    tickets = {}
+    lock = threading.Lock()
+
+    def submitter(part):
+        for i in range(part, len(graphs), 4):
+            g = graphs[i]
+            t = srv.submit(g.n, g.src, g.dst, None, 1000 + i, outs[i])
+            with lock:
+                tickets[t] = i
+
+    try:
+        threads = [threading.Thread(target=submitter, args=(p,)) for p in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        done = {}
+        while len(done) < len(graphs):
+            for c in srv.poll(64, 0.5):
+                assert c[0] not in done
+                done[c[0]] = c[1]
+        assert sorted(tickets) == sorted(done) and all(s == 0 for s in done.values())
+    finally:
+        srv.close()
+    for t, i in tickets.items():
+        assert torch.equal(outs[i], cl.embed(graphs[i], 32, 3, 1000 + i)), i
