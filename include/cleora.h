@@ -185,8 +185,8 @@ int cleora_sync(cleora_ctx *ctx, void *stream);
  * fixed order (the packing of shorter rows into work items adapts to the
  * graph by itself).  It fixes the float32 summation order of long rows, so
  * contexts that must agree bit for bit must use the same value.  0
- * restores the default, which depends only on the row layout: 512 entries
- * for rows of T of at least 1 KiB, 256 for narrower rows.  Takes effect at the next cleora_init.
+ * restores the default, 512 entries for every graph and layout.  Takes
+ * effect at the next cleora_init.
  * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 

@@ -470,7 +470,31 @@ __global__ __launch_bounds__(WPB * 64) void k_combine(const StepDesc *__restrict
     float4 acc[VPLF];
 #pragma unroll
     for (int v = 0; v < VPLF; ++v) acc[v] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t i = w; i < nch; i += WPB) {
+    // wave w adds partials w, w + WPB, ... in that order; CU of them are
+    // loaded together (a hub row has hundreds per wave)
+    constexpr int CU = VPLF >= 8 ? 1 : 8 / VPLF;
+    int64_t i = w;
+    for (; i + (int64_t)(CU - 1) * WPB < nch; i += (int64_t)CU * WPB) {
+        float4 p[CU][VPLF];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+            for (int v = 0; v < VPLF; ++v) {
+                const int ch = lane + v * 64;
+                p[u][v] = ch < cprf ? P[(b0 + i + (int64_t)u * WPB) * prow + ch]
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+#pragma unroll
+            for (int v = 0; v < VPLF; ++v) {
+                acc[v].x += p[u][v].x;
+                acc[v].y += p[u][v].y;
+                acc[v].z += p[u][v].z;
+                acc[v].w += p[u][v].w;
+            }
+    }
+    for (; i < nch; i += WPB) {
 #pragma unroll
         for (int v = 0; v < VPLF; ++v) {
             const int ch = lane + v * 64;

@@ -67,17 +67,14 @@ int32_t padded_ld(int32_t dim, int dtype)
 }
 
 // Split size: rows with more entries are split into pieces of this many
-// entries (and recombined in order).  A function of the row layout only, so
-// that a graph is summed the same way alone and in any batch; small enough
-// that one piece is a short latency chain for small graphs, large enough
-// that the float32 partial rows it writes (d*4 bytes per piece) stay under
-// 1% of the gathered bytes.  512 for rows of 1 KiB or more (measured best on
-// the 1M-node power-law graph at d = 256), 256 below.
-constexpr int32_t DEFAULT_SPLIT = 256;
-int32_t default_split(int32_t ld, int dtype)
-{
-    return (int64_t)ld * elem_size(dtype) >= 1024 ? 512 : DEFAULT_SPLIT;
-}
+// entries (and recombined in order).  The same for every graph, so that a
+// graph is summed the same way alone and in any batch; small enough that
+// one piece is a short latency chain, large enough that the float32 partial
+// rows it writes (d*4 bytes per piece) stay under 1% of the gathered bytes.
+// Measured on the 1M-node power-law graph: 512 is fastest for 1 KiB rows
+// (FP32, d = 256) and for 512-byte rows (BF16, d = 256: the recombination
+// halves against 256, the SpMM is unchanged; 1024 slows the SpMM).
+constexpr int32_t DEFAULT_SPLIT = 512;
 
 void check_dim(int32_t dim, int32_t dtype)
 {
@@ -195,7 +192,7 @@ void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
     c->dim = dim;
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
-    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_split(c->ld, dtype);
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
     const size_t ebytes = (size_t)n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
@@ -572,7 +569,7 @@ int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t
     c->dim = dim;
     c->dtype = dtype;
     c->ld = (int32_t)ld_in;
-    c->chunk = c->chunk_req > 0 ? c->chunk_req : default_split(c->ld, dtype);
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
     const size_t ebytes = (size_t)n_rows * (size_t)c->ld * elem_size(dtype);
     c->E[1].ensure(ebytes);
     cleora::plan_schedule(c, s);
