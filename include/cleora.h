@@ -94,7 +94,7 @@ int cleora_build_csr(cleora_ctx *ctx, int64_t n_nodes, int64_t n_edges, const in
  *   T_0[i][j] = k / 2^23 - 1,  k = splitmix64(seed ^ splitmix64(i*dim + j)) >> 40
  * (SplitMix64 output function of Steele, Lea and Flood, 2014), exact in
  * float32, rounded to nearest even for CLEORA_BF16.  Also plans the
- * propagation schedule for this dim and synchronises the stream once.
+ * propagation schedule for this dim, which synchronises the stream.
  * Resets the iteration count to 0.
  * Errors: E_STATE (no graph), E_INVAL (dim < 1 or above the maximum, bad
  * dtype), E_NOMEM, E_DEVICE. */
