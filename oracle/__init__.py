@@ -51,8 +51,10 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        build()
-        lib = ctypes.CDLL(LIB)
+        # ORACLE_LIB: an already built copy of the same source (the
+        # sanitizer test loads an instrumented build this way)
+        path = os.environ.get("ORACLE_LIB") or build()
+        lib = ctypes.CDLL(path)
         i64, i32, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
         p = ctypes.c_void_p
         lib.oracle_splitmix64.restype = u64
