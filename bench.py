@@ -81,6 +81,33 @@ def summarize_trace(trace_dir: str, out: str, last: int, command: str) -> None:
             f.write(f"{n:6d} {tot / n:10.4f} {tot:10.3f}  {name[:150]}\n")
 
 
+def summarize_markers(trace_dir: str, out: str, command: str) -> None:
+    """Per-range summary of a rocprofv3 --marker-trace run: the library's
+    named ranges around its entry points, host-side durations."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(trace_dir, "**", "*marker_api_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no marker_api_trace.csv under {trace_dir}")
+    agg = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            a = agg.setdefault(r["Function"], [0, 0.0, 0.0])
+            a[0] += 1
+            a[1] += d
+            a[2] = max(a[2], d)
+    with open(out, "w") as f:
+        f.write(f"# rocprofv3 marker (roctx range) summary\n# command: {command}\n")
+        f.write("# host time from entering to leaving each entry point: calls that\n"
+                "# synchronise (build, init, autotune) include their GPU work and wait for\n"
+                "# work queued before them (the previous step's iterations); propagate\n"
+                "# only queues its graph launch\n")
+        f.write(f"{'calls':>6} {'avg_ms':>10} {'max_ms':>10} {'total_ms':>10}  range\n")
+        for name, (n, tot, mx) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+            f.write(f"{n:6d} {tot / n:10.4f} {mx:10.4f} {tot:10.3f}  {name}\n")
+
+
 def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
                   copy_bytes: int, last: int) -> None:
     """HBM-side traffic per launch of the SpMM kernel from two rocprofv3
@@ -320,6 +347,10 @@ def main():
     # summarize-trace TRACE_DIR OUT LAST COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
         summarize_trace(sys.argv[2], sys.argv[3], int(sys.argv[4]), " ".join(sys.argv[5:]))
+        return
+    # summarize-markers TRACE_DIR OUT COMMAND...
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-markers":
+        summarize_markers(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
         return
     # summarize-pmc FETCH_DIR WRITE_DIR OUT COPY_BYTES LAST COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-pmc":

@@ -6,7 +6,22 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.hpp"
+
+namespace cleora {
+
+// A named range on the profiler's timeline (rocprofv3 --marker-trace) for
+// the lifetime of the object; cheap when no profiler is attached.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
+}  // namespace cleora
 
 namespace cleora {
 

@@ -435,6 +435,7 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
                      const float *w, uint32_t flags, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_build_csr");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     check_graph_sizes(n, m);
     if (m > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst is NULL");
@@ -450,6 +451,7 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
 int cleora_init(cleora_ctx *c, int32_t dim, int32_t dtype, uint64_t seed, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_init");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (!c->has_graph) return fail(CLEORA_E_STATE, "no graph: call cleora_build_csr first");
     check_dim(dim, dtype);
@@ -468,6 +470,7 @@ int cleora_build_init(cleora_ctx *c, int64_t n_nodes, int64_t n_edges, const int
                       int32_t dtype, uint64_t seed, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_build_init");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     check_graph_sizes(n_nodes, n_edges);
     if (n_edges > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst NULL");
@@ -491,6 +494,7 @@ int cleora_build_init(cleora_ctx *c, int64_t n_nodes, int64_t n_edges, const int
 int cleora_propagate(cleora_ctx *c, int32_t k, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_propagate");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding: call cleora_init first");
@@ -503,6 +507,7 @@ int cleora_propagate(cleora_ctx *c, int32_t k, void *stream)
 int cleora_get_embedding(cleora_ctx *c, void *dst, int64_t ld, int32_t dst_dtype, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_get_embedding");
     if (!c || !dst) return fail(CLEORA_E_INVAL, "NULL argument");
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding");
     if (ld < c->dim) return fail(CLEORA_E_INVAL, "ld < dim");
@@ -551,6 +556,7 @@ int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t
                           int64_t ld_out, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_propagate_rows");
     if (!c || !T_in || !out) return fail(CLEORA_E_INVAL, "NULL argument");
     check_graph_sizes(n_rows, m);
     check_graph_sizes(n_cols, 0);
@@ -679,6 +685,7 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
                     void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_autotune");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding: call cleora_init first");
     DeviceGuard g(c->device);
@@ -811,6 +818,7 @@ int cleora_expand_clique(cleora_ctx *c, int64_t n_hyper, const int64_t *offsets,
                          int64_t *n_edges, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_expand_clique");
     if (!c || !offsets || !n_edges) return fail(CLEORA_E_INVAL, "NULL argument");
     if (n_hyper < 0) return fail(CLEORA_E_INVAL, "n_hyper < 0");
     if (src && !dst) return fail(CLEORA_E_INVAL, "NULL dst");
@@ -828,6 +836,7 @@ int cleora_expand_star(cleora_ctx *c, int64_t n_nodes, int64_t n_hyper, const in
                        int64_t *n_edges, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_expand_star");
     if (!c || !offsets || !n_edges) return fail(CLEORA_E_INVAL, "NULL argument");
     if (n_hyper < 0 || n_nodes < 0 || n_nodes + n_hyper > 0x7fffffffLL)
         return fail(CLEORA_E_INVAL, "n_nodes + n_hyper must stay below 2^31");
@@ -853,6 +862,7 @@ int cleora_build_chunk(cleora_ctx *c, int64_t n_global, int64_t m, const int32_t
                        const int32_t *dst, const float *w, uint32_t flags, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_build_chunk");
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     check_graph_sizes(n_global, m);
     if (m < 1 || !src || !dst) return fail(CLEORA_E_INVAL, "a chunk needs edges");
@@ -883,6 +893,7 @@ int cleora_chunk_info(cleora_ctx *c, int64_t *n_local, int32_t *ids, float *occ,
 int cleora_merge_chunk(cleora_ctx *c, float *acc, int64_t ld_acc, float *wsum, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_merge_chunk");
     if (!c || !acc || !wsum) return fail(CLEORA_E_INVAL, "NULL argument");
     if (!c->is_chunk || !c->has_emb) return fail(CLEORA_E_STATE, "not an embedded chunk");
     if (ld_acc < c->dim) return fail(CLEORA_E_INVAL, "ld_acc < dim");
@@ -916,6 +927,7 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
                        void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_embed_batch");
     if (!c || !graphs || !out) return fail(CLEORA_E_INVAL, "NULL argument");
     if (n_graphs < 1) return fail(CLEORA_E_INVAL, "n_graphs must be >= 1");
     if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
@@ -982,6 +994,7 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
 int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream)
 {
     ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_step_multi");
     if (n < 0 || (n > 0 && !ctxs)) return fail(CLEORA_E_INVAL, "bad context list");
     if (n == 0) return CLEORA_OK;
     for (int32_t i = 0; i < n; ++i) {

@@ -141,6 +141,7 @@ struct cleora_server {
     // out of range are dropped first, with E_INPUT).
     void build_group(Group *g, hipStream_t s, HostBuf &host)
     {
+        cleora::TraceRange trace_range("cleora_server build group");
         const size_t nm = g->members.size();
         bool any_w = false;
         int64_t m_total = 0, n_total = 0;
@@ -393,6 +394,7 @@ struct cleora_server {
                 for (Group *g : active)
                     if (g->iteration < k) list.push_back(ctxs[g->slot]);
                 if (!list.empty()) {
+                    cleora::TraceRange trace_range("cleora_server step");
                     cleora::step_contexts(list.data(), (int32_t)list.size(), main_s);
                     ++steps;
                     max_active = std::max(max_active, (int32_t)list.size());
