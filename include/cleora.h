@@ -208,7 +208,10 @@ int cleora_set_schedule(cleora_ctx *ctx, int32_t pack, int32_t persistent);
  * -- and the embedding and iteration count are left as they were.
  * Choices are cached per (N, nnz, dim, dtype, split size) for the life of
  * the process, and every later cleora_init of a graph of that shape, in
- * any context, uses the cached choice.  Outputs (may be NULL): the chosen
+ * any context, uses the cached choice.  With the environment variable
+ * CLEORA_TUNE_CACHE naming a file, choices are also read from that file
+ * (once per process, also by inits that never call the autotuner) and
+ * each new choice is appended to it, one text line per graph shape.  Outputs (may be NULL): the chosen
  * packing size, 1 if the persistent grid won (else 0), and the time per
  * step in ms.  Errors: E_STATE (no embedding), E_DEVICE. */
 int cleora_autotune(cleora_ctx *ctx, int32_t *pack, int32_t *persistent, float *step_ms,

@@ -30,6 +30,52 @@ struct TuneChoice {
 std::mutex g_tune_mu;
 std::map<std::tuple<int64_t, int64_t, int32_t, int32_t, int32_t>, TuneChoice> g_tune_cache;
 
+// CLEORA_TUNE_CACHE=<path>: choices are read from that text file once per
+// process and every new choice is appended to it, one line each:
+//   n nnz dim dtype split pack persistent ms
+// Caller holds g_tune_mu.
+const char *tune_file() { return std::getenv("CLEORA_TUNE_CACHE"); }
+
+void load_tune_file_locked()
+{
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *path = tune_file();
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), f)) {
+        long long n, nnz;
+        int dim, dtype, split, pack, persist;
+        float ms;
+        if (line[0] == '#' || std::sscanf(line, "%lld %lld %d %d %d %d %d %f", &n, &nnz, &dim,
+                                          &dtype, &split, &pack, &persist, &ms) != 8)
+            continue;
+        if (pack < 16 || pack > (1 << 20) || persist < 0 || persist > 8) continue;
+        TuneChoice t;
+        t.pack = pack;
+        t.persist = persist;
+        t.ms = ms;
+        g_tune_cache.emplace(std::make_tuple((int64_t)n, (int64_t)nnz, dim, dtype, split), t);
+    }
+    std::fclose(f);
+}
+
+void append_tune_file_locked(const std::tuple<int64_t, int64_t, int32_t, int32_t, int32_t> &k,
+                             const TuneChoice &t)
+{
+    const char *path = tune_file();
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%lld %lld %d %d %d %d %d %.4f\n", (long long)std::get<0>(k),
+                 (long long)std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), t.pack,
+                 t.persist, t.ms);
+    std::fclose(f);
+}
+
 int fail(int code, const std::string &msg)
 {
     g_last_error = msg;
@@ -265,6 +311,7 @@ namespace cleora {
 int32_t tuned_pack(const cleora_ctx *c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
     auto it = g_tune_cache.find(std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk));
     return it == g_tune_cache.end() ? 0 : it->second.pack;
 }
@@ -272,6 +319,7 @@ int32_t tuned_pack(const cleora_ctx *c)
 int32_t tuned_persist(const cleora_ctx *c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file_locked();
     auto it = g_tune_cache.find(std::make_tuple(c->n, c->nnz, c->dim, c->dtype, c->chunk));
     return it == g_tune_cache.end() ? 0 : it->second.persist;
 }
@@ -694,6 +742,7 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
     TuneChoice best;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_file_locked();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) best = it->second;
     }
@@ -760,6 +809,7 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
         restore();
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = best;
+        append_tune_file_locked(key, best);
     }
     drop_graphs(c);
     c->pack_req = 0;  // the cache entry now applies to this and later inits

@@ -394,3 +394,39 @@ def test_build_init_bad_input_leaves_no_embedding(cl):
         want = cl.embed(g, 32, 2, 1)
         import torch
         assert torch.equal(c.embedding(), want)
+
+
+def test_tune_cache_file_across_processes(cl, tmp_path):
+    """CLEORA_TUNE_CACHE: a tuned choice is written once and picked up by
+    later processes, also by inits that never call the autotuner."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "import sys, gen, paper_2102_02302_amd as cl\n"
+        "g = gen.chung_lu(20_000, 150_000, 2.1, 91)\n"
+        "with cl.Context(0) as c:\n"
+        "    c.build_graph_init(g, 64, 'f32', 1)\n"
+        "    if sys.argv[1] == 'tune':\n"
+        "        t = c.autotune()\n"
+        "        print('RESULT', t['pack'], int(t['persistent']))\n"
+        "    else:\n"
+        "        s = c.schedule()\n"
+        "        print('RESULT', s['pack'], s['persistent'])\n")
+    path = tmp_path / "tune.txt"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CLEORA_TUNE_CACHE=str(path))
+
+    def run(mode):
+        r = subprocess.run([sys.executable, "-c", code, mode], cwd=root, env=env,
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stdout + r.stderr
+        return [ln for ln in r.stdout.splitlines() if ln.startswith("RESULT")][0].split()[1:]
+
+    tuned = run("tune")
+    lines = path.read_text().strip().splitlines()
+    assert len(lines) == 1 and len(lines[0].split()) == 8
+    assert lines[0].split()[5:7] == tuned
+    assert run("plain") == tuned   # planned from the file, no tuning
+    assert run("tune") == tuned    # cached: nothing new appended
+    assert len(path.read_text().strip().splitlines()) == 1
