@@ -361,10 +361,11 @@ typedef struct {
     double done_s;      /* the result is in `out` */
 } cleora_completion;
 
-/* slots: contexts (groups in flight); builders: build threads; max_group:
- * most requests built together (1: every request on its own).  flags:
- * CLEORA_DIRECTED / CLEORA_EMPTY_KEEP for every request.
- * Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+/* slots: contexts (groups in flight); budget_bytes: most summed footprint
+ * of admitted requests (0: 80% of the device memory free at creation);
+ * builders: build threads; max_group: most requests built together (1:
+ * every request on its own).  flags: CLEORA_DIRECTED / CLEORA_EMPTY_KEEP
+ * for every request.  Errors: E_INVAL, E_DEVICE, E_NOMEM. */
 int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t dtype, int32_t k,
                          int32_t slots, int64_t budget_bytes, int32_t builders, int32_t max_group,
                          uint32_t flags);

@@ -471,7 +471,7 @@ int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t d
     }
     *out = nullptr;
     if (dim < 1 || (dtype != CLEORA_F32 && dtype != CLEORA_BF16) || k < 0 || slots < 1 ||
-        budget_bytes < 1 || builders < 1 || max_group < 1 ||
+        budget_bytes < 0 || builders < 1 || max_group < 1 ||
         (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP))) {
         cleora::set_last_error("bad server parameters");
         return CLEORA_E_INVAL;
@@ -496,6 +496,13 @@ int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t d
     }
     s->staging.resize(s->ctxs.size());
     if (rc == CLEORA_OK && hipSetDevice(device) != hipSuccess) rc = CLEORA_E_DEVICE;
+    if (rc == CLEORA_OK && budget_bytes == 0) {
+        // 80% of what is free on the device now
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) rc = CLEORA_E_DEVICE;
+        else s->budget = (int64_t)(0.8 * (double)free_b);
+        if (rc == CLEORA_OK && s->budget < 1) rc = CLEORA_E_NOMEM;
+    }
     if (rc == CLEORA_OK && hipStreamCreateWithFlags(&s->main_s, hipStreamNonBlocking) != hipSuccess)
         rc = CLEORA_E_DEVICE;
     for (int32_t i = 0; i < builders && rc == CLEORA_OK; ++i) {

@@ -197,3 +197,25 @@ def test_native_server_concurrent_submitters(cl):
         srv.close()
     for t, i in tickets.items():
         assert torch.equal(outs[i], cl.embed(graphs[i], 32, 3, 1000 + i)), i
+
+
+def test_native_server_budget_from_free_memory(cl):
+    """budget 0: 80% of the free device memory.  A request whose footprint
+    is above that is refused at submit; a normal one is served."""
+    import torch
+    from paper_2102_02302_amd.serve import NativeServer
+    srv = NativeServer(32, "f32", 2, slots=2, budget_bytes=0, builders=1)
+    try:
+        g = gen.erdos_renyi(300, 1200, 95)
+        out = torch.empty((g.n, 32), device="cuda")
+        t = srv.submit(g.n, g.src, g.dst, None, 3, out)
+        got = []
+        while not got:
+            got = srv.poll(4, 1.0)
+        assert got[0][0] == t and got[0][1] == 0
+        assert torch.equal(out, cl.embed(g, 32, 2, 3))
+        tiny = np.zeros(4, np.int32)
+        with pytest.raises(cl.CleoraError):  # about 600 GB of footprint
+            srv.submit(2_000_000_000, tiny, tiny, None, 1, out)
+    finally:
+        srv.close()
