@@ -97,10 +97,15 @@ def test_chunglu1m_full_parity(cl):
     with cl.Context(0) as ctx:
         ctx.build_graph(g).init(dim, dtype, 2102).propagate(k)
         got = ctx.embedding().cpu().numpy()
+        ctx.init(dim, "bf16", 2102).propagate(k)
+        got16 = ctx.embedding("f32").cpu().numpy().astype(np.float64)
     want = oracle.embed(g, dim, k, 2102)
     err = np.abs(got.astype(np.float64) - want).max()
-    print(f"chunglu1m FP32 k={k}: max-abs {err:.3e} over {got.size} values")
+    err16, cos16 = rowwise_report(got16, want)
+    print(f"chunglu1m k={k} vs FP64 oracle, every value: FP32 max-abs {err:.3e}; "
+          f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}")
     assert err <= F32_TOL
+    assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
 
 
 def oracle_rows_after_k(g, dim, k, seed, rows, t0, label):
