@@ -81,6 +81,35 @@ def summarize_trace(trace_dir: str, out: str, last: int, command: str) -> None:
             f.write(f"{n:6d} {tot / n:10.4f} {tot:10.3f}  {name[:150]}\n")
 
 
+def summarize_counters(pmc_dir: str, out: str, last: int, command: str) -> None:
+    """Per-dispatch averages of every counter of a rocprofv3 --pmc run over
+    the SpMM kernel's last `last` dispatches (the timed steps)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {pmc_dir}")
+    per = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if SPMM in r["Kernel_Name"]:
+                per.setdefault(r["Counter_Name"], []).append(
+                    (int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    res = {"command": command, "kernel_source_sha256_16": kernel_source_hash(), "counters": {}}
+    for name, vals in sorted(per.items()):
+        vals.sort()
+        v = [x for _, x in vals][-last:] if last > 0 else [x for _, x in vals]
+        res["counters"][name] = {"per_dispatch": sum(v) / len(v), "dispatches": len(v)}
+    c = {k: v["per_dispatch"] for k, v in res["counters"].items()}
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        res["l2_hit_rate"] = c["TCC_HIT_sum"] / (c["TCC_HIT_sum"] + c["TCC_MISS_sum"])
+    if "TCC_EA0_RDREQ_sum" in c and "TCC_EA0_RDREQ_DRAM_sum" in c:
+        res["dram_share_of_l2_read_requests"] = c["TCC_EA0_RDREQ_DRAM_sum"] / c["TCC_EA0_RDREQ_sum"]
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+        f.write("\n")
+
+
 def summarize_markers(trace_dir: str, out: str, command: str) -> None:
     """Per-range summary of a rocprofv3 --marker-trace run: the library's
     named ranges around its entry points, host-side durations."""
@@ -347,6 +376,10 @@ def main():
     # summarize-trace TRACE_DIR OUT LAST COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
         summarize_trace(sys.argv[2], sys.argv[3], int(sys.argv[4]), " ".join(sys.argv[5:]))
+        return
+    # summarize-counters PMC_DIR OUT LAST COMMAND...
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
+        summarize_counters(sys.argv[2], sys.argv[3], int(sys.argv[4]), " ".join(sys.argv[5:]))
         return
     # summarize-markers TRACE_DIR OUT COMMAND...
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-markers":
