@@ -430,3 +430,67 @@ def test_tune_cache_file_across_processes(cl, tmp_path):
     assert run("plain") == tuned   # planned from the file, no tuning
     assert run("tune") == tuned    # cached: nothing new appended
     assert len(path.read_text().strip().splitlines()) == 1
+
+
+# ------------------------------------------------------ edge cases
+
+def hub_graph(n, hub_degrees, extra_m, seed):
+    """Hubs 0, 1, ... with exactly the given numbers of distinct neighbours,
+    plus random edges among the other nodes."""
+    rng = np.random.default_rng(seed)
+    src, dst = [], []
+    for h, d in enumerate(hub_degrees):
+        nb = rng.choice(np.arange(len(hub_degrees), n), d, replace=False)
+        src.append(np.full(d, h))
+        dst.append(nb)
+    a = rng.integers(len(hub_degrees), n, extra_m)
+    b = rng.integers(len(hub_degrees), n, extra_m)
+    ok = a != b
+    src.append(a[ok])
+    dst.append(b[ok])
+    return gen.Graph(n, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32),
+                     None, False, f"hubs{hub_degrees}")
+
+
+@pytest.mark.parametrize("dim,dtype", [(64, "f32"), (256, "f32"), (96, "bf16"), (512, "bf16")])
+def test_split_size_boundaries(cl, dim, dtype):
+    # rows of exactly S - 1, S, S + 1, 2S, 2S + 1 entries (S = 512) and one
+    # past the 4096-entry segmented row sums
+    g = hub_graph(9000, [511, 512, 513, 1024, 1025, 4097], 20_000, 61)
+    with cl.Context(0) as c:
+        c.build_graph(g).init(dim, dtype, 7).propagate(3)
+        assert c.schedule()["chunk"] == 512 and c.schedule()["split_rows"] >= 4
+        got = c.embedding("f32").cpu().numpy().astype(np.float64)
+    want = oracle_embed(g, dim, 3, 7)
+    if dtype == "f32":
+        assert np.abs(got - want).max() <= F32_TOL
+    else:
+        err, cmin = bf16_report(got, want)
+        assert err <= BF16_MAXABS and cmin >= BF16_MINCOS, (err, cmin)
+
+
+@pytest.mark.parametrize("dim,dtype", [(4096, "f32"), (8192, "bf16")])
+def test_maximum_dimensions(cl, dim, dtype):
+    g = hub_graph(1500, [700], 6000, 62)  # one split hub row
+    with cl.Context(0) as c:
+        c.build_graph(g).init(dim, dtype, 8).propagate(2)
+        got = c.embedding("f32").cpu().numpy().astype(np.float64)
+        with pytest.raises(cl.CleoraError):
+            c.init(dim + 1, dtype, 8)
+    want = oracle_embed(g, dim, 2, 8)
+    if dtype == "f32":
+        assert np.abs(got - want).max() <= F32_TOL
+    else:
+        err, cmin = bf16_report(got, want)
+        assert err <= BF16_MAXABS and cmin >= BF16_MINCOS, (err, cmin)
+
+
+@pytest.mark.parametrize("dim", [8, 24, 40, 200, 1000])
+def test_bf16_odd_widths(cl, dim):
+    # every group count of the narrow-row kernels (16, 16, 8, 2, 1 rows per
+    # wave) and partial 16-byte vectors
+    g = zoo()[3]
+    got = gpu_embed(cl, g, dim, 3, seed=10, dtype="bf16")
+    want = oracle_embed(g, dim, 3, 10)
+    err, cmin = bf16_report(got, want)
+    assert err <= BF16_MAXABS and cmin >= BF16_MINCOS, (dim, err, cmin)
