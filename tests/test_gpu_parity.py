@@ -494,3 +494,18 @@ def test_bf16_odd_widths(cl, dim):
     want = oracle_embed(g, dim, 3, 10)
     err, cmin = bf16_report(got, want)
     assert err <= BF16_MAXABS and cmin >= BF16_MINCOS, (dim, err, cmin)
+
+
+@pytest.mark.parametrize("empty_keep", [False, True])
+def test_batch_directed_weighted_equals_solo(cl, empty_keep):
+    graphs = [gen.random_graph(n, 4 * n, 70 + i, directed=True, weighted=True, loops=True,
+                               multi=True) for i, n in enumerate((300, 1200, 50, 4000))]
+    seeds = [11, 12, 13, 14]
+    with cl.Context(0) as ctx:
+        outs = cl.embed_batch(ctx, graphs, 40, 3, seeds, directed=True, empty_keep=empty_keep)
+        outs = [o.cpu().numpy() for o in outs]
+    for g, s, o in zip(graphs, seeds, outs):
+        solo = gpu_embed(cl, g, 40, 3, seed=s, empty_keep=empty_keep).astype(np.float32)
+        assert np.array_equal(o, solo), g.name
+        want = oracle_embed(g, 40, 3, s, empty_keep=empty_keep)
+        assert np.abs(o - want).max() <= F32_TOL

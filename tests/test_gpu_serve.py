@@ -219,3 +219,28 @@ def test_native_server_budget_from_free_memory(cl):
             srv.submit(2_000_000_000, tiny, tiny, None, 1, out)
     finally:
         srv.close()
+
+
+def test_native_server_directed_weighted(cl):
+    """A server for directed graphs: weighted requests with loops, repeated
+    pairs and sinks, grouped, give their solo results."""
+    import torch
+    from paper_2102_02302_amd.serve import NativeServer
+    graphs = [gen.random_graph(n, 3 * n, 120 + i, directed=True, weighted=True, loops=True,
+                               multi=True) for i, n in enumerate((80, 900, 300, 2500, 40))]
+    outs = [torch.empty((g.n, 24), device="cuda") for g in graphs]
+    torch.cuda.synchronize()
+    srv = NativeServer(24, "f32", 3, slots=2, budget_bytes=1 << 30, builders=1, max_group=4,
+                       directed=True)
+    try:
+        tickets = {srv.submit(g.n, g.src, g.dst, g.w, 500 + i, outs[i]): i
+                   for i, g in enumerate(graphs)}
+        done = {}
+        while len(done) < len(graphs):
+            for c in srv.poll(8, 0.5):
+                done[c[0]] = c[1]
+        assert all(s == 0 for s in done.values())
+    finally:
+        srv.close()
+    for t, i in tickets.items():
+        assert torch.equal(outs[i], cl.embed(graphs[i], 24, 3, 500 + i)), i
