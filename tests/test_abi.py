@@ -75,3 +75,34 @@ def test_error_paths_without_gpu(lib):
     import torch
     if not torch.cuda.is_available():
         assert lib.cleora_create(ctypes.byref(h), 0) == _lib.E_DEVICE
+
+
+def test_more_error_paths_without_gpu(lib):
+    """Argument checks that answer before any device work."""
+    import ctypes
+    from paper_2102_02302_amd import _lib
+    null = None
+    assert lib.cleora_build_init(null, 10, 0, null, null, null, 0, 16, 0, 1, null) == _lib.E_INVAL
+    assert lib.cleora_set_schedule(null, 0, -1) == _lib.E_INVAL
+    assert lib.cleora_autotune(null, null, null, null, null) == _lib.E_INVAL
+    assert lib.cleora_schedule_info(null, null, null, null, null, null, null) == _lib.E_INVAL
+    assert lib.cleora_set_chunk(null, 0) == _lib.E_INVAL
+    # server: null out, and bad parameters, rejected before any context is made
+    assert lib.cleora_server_create(null, 0, 16, 0, 2, 2, 1 << 20, 1, 1, 0) == _lib.E_INVAL
+    h = ctypes.c_void_p()
+    for args in ((0, 0, 0, 2, 2, 1 << 20, 1, 1, 0),      # dim 0
+                 (0, 16, 7, 2, 2, 1 << 20, 1, 1, 0),     # bad dtype
+                 (0, 16, 0, -1, 2, 1 << 20, 1, 1, 0),    # k < 0
+                 (0, 16, 0, 2, 0, 1 << 20, 1, 1, 0),     # no slots
+                 (0, 16, 0, 2, 2, -1, 1, 1, 0),          # negative budget
+                 (0, 16, 0, 2, 2, 1 << 20, 0, 1, 0),     # no builders
+                 (0, 16, 0, 2, 2, 1 << 20, 1, 0, 0),     # groups of 0
+                 (0, 16, 0, 2, 2, 1 << 20, 1, 1, 64)):   # unknown flag
+        assert lib.cleora_server_create(ctypes.byref(h), *args) == _lib.E_INVAL, args
+        assert not h.value
+    assert lib.cleora_server_submit(null, null, null) == _lib.E_INVAL
+    n = ctypes.c_int32()
+    assert lib.cleora_server_poll(null, null, 0, ctypes.byref(n), 0.0) == _lib.E_INVAL
+    assert lib.cleora_server_stats(null, null, null, null, null, null, null) == _lib.E_INVAL
+    assert lib.cleora_server_now(null) == 0.0
+    lib.cleora_server_destroy(null)
