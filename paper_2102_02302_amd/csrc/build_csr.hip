@@ -4,19 +4,22 @@
 //
 // Pipeline (caller's stream, one host synchronisation at the end):
 //   1. one 64-bit key per stored entry, key = row << cb | col (cb = bits of
-//      the column count - 1); a loop's second copy and invalid edges get a
-//      key above every valid one; optional float32 weight as payload.  Rows
-//      and columns may number differently (new nodes against existing ones);
-//      undirected graphs are square;
-//   2. stable LSD radix sort of the keys (8-bit digits, reduce-then-scan:
-//      per-tile digit counts, one device scan, stable scatter through LDS) --
-//      no global atomics, so hub rows cost no more than other rows, and
-//      repeated (a, b) pairs keep their input order;
+//      the column count - 1); a loop's second copy and invalid edges get
+//      the key of row n, column 0, above every valid one; optional float32
+//      weight as payload.  Rows and columns may number differently (new
+//      nodes against existing ones); undirected graphs are square;
+//   2. stable LSD radix sort of the keys (8-bit digits over bits(n + 1) +
+//      cb bits, reduce-then-scan: per-tile digit counts, one device scan,
+//      stable scatter through LDS, each wave ranking its own part of the
+//      tile) -- no global atomics, so hub rows cost no more than other rows,
+//      and repeated (a, b) pairs keep their input order;
 //   3. mark the first entry of each run of equal keys, scan, compact: one
 //      merged entry per pair with e_ab summed in float64 in input order;
 //   4. row pointers by binary search over the merged keys;
 //   5. deg(a) = sum_b e_ab in float64 and M_ab = e_ab / deg(a) in float32
-//      (one wave per row, one block per long row, fixed reduction order).
+//      (four rows per wave; rows over LONG_ROW entries in LONG_ROW-entry
+//      segments, one wave each, added in segment order: a fixed reduction
+//      order everywhere).
 #include "internal.hpp"
 
 #include <algorithm>
