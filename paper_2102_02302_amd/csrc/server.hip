@@ -93,6 +93,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct cleora_server {
     int device = 0;
     int32_t dim = 0, dtype = 0, k = 0, max_group = 1;
+    int32_t pack_threads = 4;  // threads that copy one large group's edges
     uint32_t flags = 0;
     int64_t budget = 0;
     std::vector<cleora_ctx *> ctxs;
@@ -166,21 +167,49 @@ struct cleora_server {
             eoff[i] = e;
             seeds[i] = q.seed;
             g->members[i]->row0 = r;
-            const bool *dv = g->members[i]->on_dev;
-            if (q.n_edges > 0) {
-                if (!dv[0]) std::memcpy(h + off_src + 4 * e, q.src, 4 * (size_t)q.n_edges);
-                if (!dv[1]) std::memcpy(h + off_dst + 4 * e, q.dst, 4 * (size_t)q.n_edges);
-                if (any_w) {
-                    float *wd = reinterpret_cast<float *>(h + off_w) + e;
-                    if (!q.w) std::fill(wd, wd + q.n_edges, 1.0f);
-                    else if (!dv[2]) std::memcpy(wd, q.w, 4 * (size_t)q.n_edges);
-                }
-            }
             e += q.n_edges;
             r += q.n_nodes;
         }
         row0[nm] = r;
         eoff[nm] = e;
+        // the members' host edge arrays into the pinned staging; a large
+        // group is copied by several threads (the copy, not the GPU, bounds
+        // the builders of a busy server)
+        auto pack = [&](size_t i0, size_t i1) {
+            for (size_t i = i0; i < i1; ++i) {
+                const cleora_request &q = g->members[i]->r;
+                const bool *dv = g->members[i]->on_dev;
+                const int64_t at = eoff[i];
+                if (q.n_edges <= 0) continue;
+                if (!dv[0]) std::memcpy(h + off_src + 4 * at, q.src, 4 * (size_t)q.n_edges);
+                if (!dv[1]) std::memcpy(h + off_dst + 4 * at, q.dst, 4 * (size_t)q.n_edges);
+                if (any_w) {
+                    float *wd = reinterpret_cast<float *>(h + off_w) + at;
+                    if (!q.w) std::fill(wd, wd + q.n_edges, 1.0f);
+                    else if (!dv[2]) std::memcpy(wd, q.w, 4 * (size_t)q.n_edges);
+                }
+            }
+        };
+        const int64_t pack_bytes = (any_w ? 12 : 8) * m_total;
+        const size_t parts =
+            std::min<size_t>(nm, pack_bytes >= (8 << 20) ? (size_t)pack_threads : 1);
+        if (parts <= 1) {
+            pack(0, nm);
+        } else {
+            // split the members into `parts` runs of about equal edge counts
+            std::vector<std::thread> th;
+            size_t i0 = 0;
+            for (size_t p = 0; p < parts && i0 < nm; ++p) {
+                const int64_t goal = (int64_t)((double)m_total * (double)(p + 1) / (double)parts);
+                size_t i1 = i0 + 1;
+                while (i1 < nm && eoff[i1] < goal) ++i1;
+                if (p + 1 == parts) i1 = nm;
+                if (p + 1 < parts) th.emplace_back(pack, i0, i1);
+                else pack(i0, i1);
+                i0 = i1;
+            }
+            for (std::thread &t : th) t.join();
+        }
         cleora::DevBuf &st = staging[g->slot];
         st.ensure(total);
         CLEORA_HIP(hipMemcpyAsync(st.p, host.p, total, hipMemcpyHostToDevice, s));
