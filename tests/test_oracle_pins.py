@@ -453,6 +453,30 @@ def test_chunked_hand_example():
     assert np.allclose(got[1], (nrm(T0[0]) + nrm(T0[2])) / 2, atol=1e-15)
 
 
+def test_chunked_unequal_occurrence_weights():
+    # node 1 has two edges in chunk A ({1,0}, {1,3}) and one in chunk B
+    # ({1,2}); k = 1: T_A[1] = normalise(T0[0] + T0[3]), T_B[1] =
+    # normalise(T0[2]), merged with weights 2/3 and 1/3 (Algorithm 1)
+    g = gen.Graph(4, np.array([1, 1, 1], np.int32), np.array([0, 3, 2], np.int32), None, False)
+    T0 = oracle.init(9, 4, 5)
+    nrm = lambda x: x / np.linalg.norm(x)  # noqa: E731
+    got = oracle.embed_chunked(g, [np.array([0, 1]), np.array([2])], 5, 1, 9)
+    want1 = (2 * nrm(T0[0] + T0[3]) + nrm(T0[2])) / 3
+    assert np.allclose(got[1], want1, atol=1e-15)
+    assert np.allclose(got[0], nrm(T0[1]), atol=1e-15)   # one chunk only
+    assert np.allclose(got[2], nrm(T0[1]), atol=1e-15)
+
+
+def test_chunked_repeated_pair_counts_twice():
+    # the pair {1,0} twice in chunk A: node 1 occurs twice there (entries
+    # before merging), once in chunk B ({1,2})
+    g = gen.Graph(3, np.array([1, 1, 1], np.int32), np.array([0, 0, 2], np.int32), None, False)
+    T0 = oracle.init(10, 3, 6)
+    nrm = lambda x: x / np.linalg.norm(x)  # noqa: E731
+    got = oracle.embed_chunked(g, [np.array([0, 1]), np.array([2])], 6, 1, 10)
+    assert np.allclose(got[1], (2 * nrm(T0[0]) + nrm(T0[2])) / 3, atol=1e-15)
+
+
 # ------------------------------------------------- hypergraph expansion
 
 def test_expansions_of_the_papers_example():
