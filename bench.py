@@ -348,7 +348,7 @@ def parse():
     ap.add_argument("--batched", action="store_true",
                     help="run the batched-form benchmark instead (many graphs per call)")
     ap.add_argument("--batch", type=int, default=512, help="graphs in the batched benchmark")
-    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--requests", type=int, default=10_000)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gib", type=int, default=64)
