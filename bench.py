@@ -270,6 +270,73 @@ def _served_runs(args, jobs, nnz_of, graphs, dim, k, server) -> dict:
     return out
 
 
+def blocked_main(args) -> dict:
+    """Column-blocked form (cleora_embed_blocked): the workload's T_k computed
+    ``--blocked`` columns at a time, against init + propagate on the same
+    graph (both after one CSR build, which is not timed).  The blocked form
+    runs k(k+1)/2 + k block iterations for k of the whole width; its device
+    buffers are two N x block embeddings instead of two N x d."""
+    import torch
+
+    import gen
+    import paper_2102_02302_amd as cl
+
+    spec = gen.WORKLOADS[args.workload]
+    dim, block = spec["dim"], args.blocked
+    k = args.k if args.k is not None else spec["k"]
+    dtype = args.dtype or spec["dtype"]
+    g = _cached_graph(args.graph_cache, args.workload, spec)
+    print(f"[blocked] {args.workload}: n={g.n} m={g.m} d={dim} block={block} k={k}", flush=True)
+    dev = torch.device("cuda", 0)
+    src = torch.as_tensor(g.src).to(dev)
+    dst = torch.as_tensor(g.dst).to(dev)
+    w = torch.as_tensor(g.w).to(dev) if g.w is not None else None
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    ctx = cl.Context(0)
+    ctx.build_csr(g.n, src, dst, w, directed=g.directed)
+    nnz = ctx.info()["nnz"]
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps
+
+    def plain():
+        ctx.init(dim, dtype, 2102)
+        ctx.propagate(k)
+
+    out_dev = torch.empty((g.n, dim), dtype=tdt, device=dev)
+    out_host = torch.empty((g.n, dim), dtype=tdt, pin_memory=True)
+    plain_ms = timed(plain)
+    print(f"[blocked] init + propagate: {plain_ms:.3f} ms", flush=True)
+    ref = ctx.embedding()
+    dev_ms = timed(lambda: ctx.embed_blocked(dim, block, k, dtype, 2102, out=out_dev))
+    print(f"[blocked] blocked, device output: {dev_ms:.3f} ms", flush=True)
+    host_ms = timed(lambda: ctx.embed_blocked(dim, block, k, dtype, 2102, out=out_host))
+    print(f"[blocked] blocked, pinned host output: {host_ms:.3f} ms", flush=True)
+    diff = float((out_dev.float() - ref.float()).abs().max())
+    same_host = bool(torch.equal(out_host, out_dev.cpu()))
+    ctx.close()
+    esz = 2 if dtype == "bf16" else 4
+    ld_b = -(-min(block, dim) * esz // 16) * 16 // esz
+    ld = -(-dim * esz // 16) * 16 // esz
+    n_blocks = -(-dim // block)
+    return {"workload": args.workload, "n_nodes": g.n, "nnz": nnz, "dim": dim, "block": block,
+            "blocks": n_blocks, "k": k, "dtype": dtype,
+            "plain_ms": round(plain_ms, 3), "blocked_ms": round(dev_ms, 3),
+            "blocked_host_out_ms": round(host_ms, 3),
+            "slowdown": round(dev_ms / plain_ms, 3),
+            "block_iterations_ratio": (k * (k + 1) // 2 + k) / k,
+            "embedding_buffers_bytes": {"plain": 2 * g.n * ld * esz,
+                                        "blocked": 2 * g.n * ld_b * esz},
+            "max_abs_vs_plain": diff, "host_output_same_bits": same_host}
+
+
 def batched_main(args) -> dict:
     """Batched form: many independent graphs of uneven size (shapes of the
     served stream: Chung-Lu, N log-uniform in [100, 200k], mean degree
@@ -348,6 +415,8 @@ def parse():
     ap.add_argument("--batched", action="store_true",
                     help="run the batched-form benchmark instead (many graphs per call)")
     ap.add_argument("--batch", type=int, default=512, help="graphs in the batched benchmark")
+    ap.add_argument("--blocked", type=int, default=0,
+                    help="run the column-blocked form instead, this many columns per block")
     ap.add_argument("--requests", type=int, default=10_000)
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--slots", type=int, default=64)
@@ -406,6 +475,18 @@ def main():
                           "config": {"workload": "batch of Chung-Lu graphs",
                                      "graphs": res["graphs"]},
                           "batched": res}), flush=True)
+        return
+    if args.blocked:
+        res = blocked_main(args)
+        print(json.dumps({"metric": "column-blocked T_k (useful nnz·d·k per second)",
+                          "value": round(res["k"] * res["nnz"] * res["dim"]
+                                         / (res["blocked_ms"] * 1e-3) / 1e9, 3),
+                          "unit": "GEdge-dims/s", "higher_is_better": True, "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": res["blocked_ms"], "dtype": res["dtype"],
+                          "data": "synthetic",
+                          "config": {"workload": args.workload, "block": args.blocked},
+                          "blocked": res}), flush=True)
         return
     if args.served:
         res = served_main(args)

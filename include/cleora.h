@@ -117,6 +117,31 @@ int cleora_build_init(cleora_ctx *ctx, int64_t n_nodes, int64_t n_edges, const i
  * bit.  Errors: E_INVAL (k < 0), E_STATE (no embedding), E_DEVICE. */
 int cleora_propagate(cleora_ctx *ctx, int32_t k, void *stream);
 
+/* T_k of the context's graph for an embedding too wide to keep two N x dim
+ * buffers in device memory (graphs larger than HBM, Section 3.2 and the
+ * paper's memory limits in Section 5): the result of cleora_init(dim,
+ * dtype, seed) + cleora_propagate(k), computed `block` columns at a time.
+ * Columns interact only through the row norms, so pass t = 1..k runs each
+ * block of T_0 through the t - 1 known row scalings and sums its share of
+ * the squared row norms of iteration t; a final pass writes each block of
+ * T_k.  Cost: k(k+1)/2 + k block iterations over dim/block blocks
+ * (k iterations for the whole width otherwise).  Device memory: two
+ * N x block embedding buffers, (k + 1) N floats and the schedule.
+ *   block   columns per block, >= 1 (block >= dim: one block)
+ *   out     N x dim (dtype), row stride ld_out >= dim elements; device or
+ *           host memory (pinned for speed); written block by block
+ * Results: T_0 entries are the same as cleora_init's (keyed by the full
+ * width); every iteration equals the unblocked one except for the order in
+ * which a row's squared norm is summed (block by block, FP32), and with a
+ * single block the result is bit-identical to init + propagate.  Rows
+ * follow the graph's CLEORA_EMPTY_KEEP flag.  The context keeps its graph
+ * and holds no embedding afterwards (E_STATE for cleora_propagate until
+ * the next cleora_init).  Synchronises `stream`.
+ * Errors: E_INVAL (NULL, dim/dtype, block < 1, k < 0, ld_out < dim),
+ * E_STATE (no graph), E_NOMEM, E_DEVICE. */
+int cleora_embed_blocked(cleora_ctx *ctx, int32_t dim, int32_t block, int32_t dtype, uint64_t seed,
+                         int32_t k, void *out, int64_t ld_out, void *stream);
+
 /* Copy the current N x dim embedding into dst (device or host memory; a
  * host destination should be pinned) with a row stride of ld elements
  * (ld >= dim).  dst_dtype must equal the context dtype, or be CLEORA_F32

@@ -15,7 +15,8 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, DIRECTED, EMPTY_KEEP, F32, CleoraError, load  # noqa: F401
 
-__all__ = ["Context", "embed", "embed_batch", "embed_chunked", "embed_new_nodes", "step_multi",
+__all__ = ["Context", "embed", "embed_batch", "embed_blocked", "embed_chunked",
+           "embed_new_nodes", "step_multi",
            "footprint_bytes", "CleoraError",
            "F32", "BF16", "DIRECTED", "EMPTY_KEEP", "load"]
 
@@ -156,6 +157,29 @@ class Context:
     def propagate(self, k: int, stream=None) -> "Context":
         _lib.check(self._lib.cleora_propagate(self._h, int(k), _stream(stream)))
         return self
+
+    def embed_blocked(self, dim: int, block: int, k: int, dtype="f32", seed: int = 0, out=None,
+                      stream=None):
+        """T_k of the context's graph computed ``block`` columns at a time
+        (for embeddings too wide for two N x dim device buffers): the result
+        of init(dim, dtype, seed) + propagate(k) up to the order of each
+        row's squared-norm sum.  ``out`` is an N x dim tensor of the dtype
+        (device, or pinned host memory for graphs larger than the device);
+        a device tensor is allocated when it is None.  The context keeps its
+        graph and holds no embedding afterwards."""
+        torch = _torch()
+        code = _dtype_code(dtype)
+        tdt = torch.float32 if code == F32 else torch.bfloat16
+        n = self.info()["n"]
+        if out is None:
+            out = torch.empty((n, dim), dtype=tdt, device=self.device)
+        if out.dtype != tdt or out.dim() != 2 or out.shape[0] != n or out.shape[1] < dim \
+                or out.stride(1) != 1:
+            raise ValueError("out must be an N x dim tensor of the dtype with unit column stride")
+        _lib.check(self._lib.cleora_embed_blocked(self._h, int(dim), int(block), code,
+                                                  int(seed) & (2**64 - 1), int(k),
+                                                  out.data_ptr(), out.stride(0), _stream(stream)))
+        return out
 
     def sync(self, stream=None) -> None:
         _lib.check(self._lib.cleora_sync(self._h, _stream(stream)))
@@ -308,6 +332,16 @@ def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
         ctx.build_graph_init(g, dim, dtype, seed, empty_keep=empty_keep)
         ctx.propagate(k)
         return ctx.embedding()
+
+
+def embed_blocked(g, dim: int, block: int, k: int, seed: int = 0, dtype="f32",
+                  device: int = 0, empty_keep: bool = False, out=None):
+    """Whole path for one graph with the embedding computed ``block`` columns
+    at a time (``Context.embed_blocked``); same result as ``embed`` up to
+    the order of each row's squared-norm sum."""
+    with Context(device) as ctx:
+        ctx.build_graph(g, empty_keep=empty_keep)
+        return ctx.embed_blocked(dim, block, k, dtype, seed, out=out)
 
 
 def embed_new_nodes(base: Context, n_new: int, new_ids, old_ids, w=None,

@@ -60,6 +60,12 @@ struct StepDesc {
     int32_t chunk;
     uint32_t flags;
     int32_t persist;  // SpMM grid: 0 = one wave per item, m > 0 = m x the resident blocks
+    // Column-blocked form (both null otherwise, and in multi-context
+    // launches): with row_ss, each row's squared norm is added to
+    // row_ss[r] and nothing is stored; with row_scale, row r is scaled by
+    // row_scale[r] instead of being normalised.
+    const float *row_scale;
+    float *row_ss;
 };
 
 // Kernel variant for an embedding layout.
@@ -86,10 +92,13 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
 // local indices), or a single graph when n_graphs == 1 and row0 == nullptr.
 // With ids != nullptr, row i uses global index ids[i] (chunks of a graph).
 // max_blocks caps the grid (0: as many blocks as the work allows), so that
-// the init can run beside other work instead of filling every CU.
+// the init can run beside other work instead of filling every CU.  With
+// dfull > 0 the rows are columns [j0, j0 + dim) of a dfull-wide T_0 (entry
+// (i, j0 + j) keyed by i * dfull + j0 + j).
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
                  const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
-                 const int32_t *ids = nullptr, int64_t max_blocks = 0);
+                 const int32_t *ids = nullptr, int64_t max_blocks = 0, int32_t dfull = 0,
+                 int32_t j0 = 0);
 
 // Hypergraph expansion (expand.hip).  expand_clique returns the edge count
 // (and writes nothing when src is null).
@@ -137,6 +146,8 @@ struct cleora_ctx {
     int32_t persist = 0, persist_req = -1;  // SpMM grid (StepDesc::persist); -1: not forced
     int64_t n_split = 0, n_buckets = 0, n_long = 0;
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
+    // column-blocked form: per-row 1/norm of iterations 1..k, squared norms
+    cleora::DevBuf blk_norms;
 
     // build temporaries (grow-only)
     cleora::DevBuf t_edges, t_wts, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
@@ -183,4 +194,9 @@ void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int6
                           const int64_t *d_eoff, const uint64_t *d_seeds, uint32_t flags,
                           int32_t dim, int32_t dtype, hipStream_t s);
 void set_last_error(const std::string &msg);
+// Column-blocked T_k (blocked.hip): dim columns, `block` at a time, into
+// out (row stride ld_out elements).  The context's graph stays; its
+// embedding buffers are reused as block buffers.
+void embed_blocked(cleora_ctx *c, int32_t dim, int32_t block, int32_t dtype, uint64_t seed,
+                   int32_t k, void *out, int64_t ld_out, hipStream_t s);
 }  // namespace cleora

@@ -18,6 +18,13 @@
 // that gather G neighbours at once and are summed at the end.  Products and
 // sums are float32 FMAs; the row norm is a wave reduction in the epilogue,
 // so T_t is written once and never re-read by this iteration.
+//
+// Column-blocked form.  Columns of T interact only through the row norms,
+// so an embedding too wide for device memory is propagated a block of
+// columns at a time.  For that the SpMM has two more epilogues (template
+// flag EXT): add the block's share of each row's squared norm to a vector
+// (no store), or scale each row by a given factor (1/norm of the whole row)
+// instead of normalising it.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -58,7 +65,8 @@ __device__ __forceinline__ float uniform_entry(uint64_t seed, int64_t i, int32_t
 template <typename T>
 __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
                        const int64_t *__restrict__ row0, const uint64_t *__restrict__ seeds,
-                       int n_graphs, uint64_t seed0, const int32_t *__restrict__ ids)
+                       int n_graphs, uint64_t seed0, const int32_t *__restrict__ ids,
+                       int32_t dfull, int32_t j0)
 {
     constexpr int EPV = 16 / sizeof(T);
     const int64_t vpr = ld / EPV;
@@ -84,7 +92,7 @@ __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
 #pragma unroll
         for (int e = 0; e < EPV; ++e) {
             const int32_t j = v * EPV + e;
-            x[e] = j < dim ? uniform_entry(seed, local, dim, j) : 0.0f;
+            x[e] = j < dim ? uniform_entry(seed, local, dfull, j0 + j) : 0.0f;
         }
         uint4 out;
         if constexpr (sizeof(T) == 4) {
@@ -319,14 +327,17 @@ __device__ __forceinline__ void reduce_groups(float (&acc)[VPL][EPV])
 
 // One wave's work item of the fused SpMM + normalise step: either a chunk
 // of a split row (partial sum to `partial`) or a packed group of rows
-// (normalised rows to Eout).
-template <typename T, int G, int VPL, int U>
+// (normalised rows to Eout).  With EXT, the column-blocked epilogues: a
+// non-null row_ss receives each row's squared norm (added, nothing
+// stored), else row r is scaled by row_scale[r].
+template <typename T, int G, int VPL, int U, bool EXT>
 __device__ __forceinline__ void spmm_item(
     int64_t wave, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const float *__restrict__ val, const uint4 *__restrict__ Ein, uint4 *__restrict__ Eout,
     float *__restrict__ partial, const int2 *__restrict__ split_items,
     const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
-    int chunk, uint32_t flags, int cpr)
+    int chunk, uint32_t flags, int cpr, const float *__restrict__ row_scale,
+    float *__restrict__ row_ss)
 {
     constexpr int EPV = EmbT<T>::EPV;
     constexpr int LPG = WAVE / G;
@@ -390,7 +401,17 @@ __device__ __forceinline__ void spmm_item(
 #pragma unroll
             for (int e = 0; e < EPV; ++e) ss = fmaf(acc[v][e], acc[v][e], ss);
         ss = group_sum<LPG>(ss);
-        const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
+        float inv;
+        if constexpr (EXT) {
+            if (row_ss) {
+                // every group holds the whole row's sum after reduce_groups
+                if (lane == 0) row_ss[r] += ss;
+                continue;
+            }
+            inv = row_scale[r];
+        } else {
+            inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
+        }
         if (grp == 0) {
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
@@ -419,18 +440,20 @@ __device__ __forceinline__ int64_t wave_id()
 // takes items wave, wave + waves in grid, ...: with one wave per item the
 // loop runs once; with a grid of the resident waves only, the kernel is
 // persistent (which of the two is faster is the autotuner's call).
-template <typename T, int G, int VPL, int U>
+template <typename T, int G, int VPL, int U, bool EXT>
 __global__ __launch_bounds__(256) void k_spmm_norm(
     const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
     const float *__restrict__ val, const uint4 *__restrict__ Ein, uint4 *__restrict__ Eout,
     float *__restrict__ partial, const int2 *__restrict__ split_items,
     const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
-    int chunk, uint32_t flags, int cpr)
+    int chunk, uint32_t flags, int cpr, const float *__restrict__ row_scale,
+    float *__restrict__ row_ss)
 {
     const int64_t items = n_split + n_buckets, stride = (int64_t)gridDim.x * 4;
     for (int64_t w = wave_id(); w < items; w += stride)
-        spmm_item<T, G, VPL, U>(w, rp, col, val, Ein, Eout, partial, split_items, bucket_row,
-                                n_split, n_buckets, ld, chunk, flags, cpr);
+        spmm_item<T, G, VPL, U, EXT>(w, rp, col, val, Ein, Eout, partial, split_items,
+                                     bucket_row, n_split, n_buckets, ld, chunk, flags, cpr,
+                                     row_scale, row_ss);
 }
 
 // Several graphs (continuous batching): each item's graph is found in the
@@ -442,11 +465,11 @@ __global__ __launch_bounds__(256) void k_spmm_norm_multi(const StepDesc *__restr
     const int64_t stride = (int64_t)gridDim.x * 4;
     for (int64_t w = wave_id(); w < items; w += stride) {
         const StepDesc &D = descs[find_desc(descs, n_desc, w, false)];
-        spmm_item<T, G, VPL, U>(w - D.wave_begin, D.rp, D.col, D.val,
-                                reinterpret_cast<const uint4 *>(D.Ein),
-                                reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items,
-                                D.bucket_row, D.n_split, D.n_buckets, D.ld, D.chunk, D.flags,
-                                cpr);
+        spmm_item<T, G, VPL, U, false>(w - D.wave_begin, D.rp, D.col, D.val,
+                                       reinterpret_cast<const uint4 *>(D.Ein),
+                                       reinterpret_cast<uint4 *>(D.Eout), D.partial,
+                                       D.split_items, D.bucket_row, D.n_split, D.n_buckets, D.ld,
+                                       D.chunk, D.flags, cpr, nullptr, nullptr);
     }
 }
 
@@ -533,7 +556,11 @@ __global__ __launch_bounds__(WPB * 64) void k_combine(const StepDesc *__restrict
         ss = fmaf(acc[v].w, acc[v].w, ss);
     }
     ss = wave_sum(ss);
-    const float inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
+    if (D.row_ss) {  // column-blocked form: the squared norm only
+        if (lane == 0) D.row_ss[row] += ss;
+        return;
+    }
+    const float inv = D.row_scale ? D.row_scale[row] : (ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f);
 #pragma unroll
     for (int v = 0; v < VPLF; ++v) {
         const int ch = lane + v * 64;
@@ -568,7 +595,7 @@ int64_t resident_blocks(K kernel)
     return (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
 }
 
-template <typename T, int G, int VPL, int U>
+template <typename T, int G, int VPL, int U, bool EXT>
 void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_t waves, int cpr,
                  int32_t persist, hipStream_t s)
 {
@@ -576,7 +603,7 @@ void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_
     if (persist > 0) {
         // per kernel instance, queried once (at init: see prime_spmm); every
         // device this library runs on is a gfx950
-        static const int64_t res1 = resident_blocks(k_spmm_norm<T, G, VPL, U>);
+        static const int64_t res1 = resident_blocks(k_spmm_norm<T, G, VPL, U, EXT>);
         static const int64_t resm = resident_blocks(k_spmm_norm_multi<T, G, VPL, U>);
         blocks = std::min(blocks, (int64_t)persist * (host ? res1 : resm));
     }
@@ -584,10 +611,10 @@ void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_
     if (blocks > 0x7fffffffLL) throw Error(CLEORA_E_INVAL, "propagation grid too large");
     if (host) {
         const StepDesc &D = *host;
-        k_spmm_norm<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(
+        k_spmm_norm<T, G, VPL, U, EXT><<<(unsigned)blocks, 256, 0, s>>>(
             D.rp, D.col, D.val, reinterpret_cast<const uint4 *>(D.Ein),
             reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items, D.bucket_row, D.n_split,
-            D.n_buckets, D.ld, D.chunk, D.flags, cpr);
+            D.n_buckets, D.ld, D.chunk, D.flags, cpr, D.row_scale, D.row_ss);
     } else {
         k_spmm_norm_multi<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, waves,
                                                                          cpr);
@@ -595,29 +622,41 @@ void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_
     CLEORA_LAUNCH_CHECK();
 }
 
-template <typename T>
-void spmm_dispatch(const Variant &v, const StepDesc *host, const StepDesc *descs, int n_desc,
-                   int64_t waves, int32_t persist, hipStream_t s)
+template <typename T, bool EXT>
+void spmm_dispatch_ext(const Variant &v, const StepDesc *host, const StepDesc *descs, int n_desc,
+                       int64_t waves, int32_t persist, hipStream_t s)
 {
+    const int c = v.cpr;
     if (v.VPL == 1) {
         switch (v.G) {
-        case 1: return spmm_launch<T, 1, 1, 8>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 2: return spmm_launch<T, 2, 1, 4>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 4: return spmm_launch<T, 4, 1, 2>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 8: return spmm_launch<T, 8, 1, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 16: return spmm_launch<T, 16, 1, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 1: return spmm_launch<T, 1, 1, 8, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 2: return spmm_launch<T, 2, 1, 4, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 4: return spmm_launch<T, 4, 1, 2, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 8: return spmm_launch<T, 8, 1, 1, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 16: return spmm_launch<T, 16, 1, 1, EXT>(host, descs, n_desc, waves, c, persist, s);
         default: break;
         }
     } else {
         switch (v.VPL) {
-        case 2: return spmm_launch<T, 1, 2, 4>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 4: return spmm_launch<T, 1, 4, 2>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 8: return spmm_launch<T, 1, 8, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
-        case 16: return spmm_launch<T, 1, 16, 1>(host, descs, n_desc, waves, v.cpr, persist, s);
+        case 2: return spmm_launch<T, 1, 2, 4, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 4: return spmm_launch<T, 1, 4, 2, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 8: return spmm_launch<T, 1, 8, 1, EXT>(host, descs, n_desc, waves, c, persist, s);
+        case 16: return spmm_launch<T, 1, 16, 1, EXT>(host, descs, n_desc, waves, c, persist, s);
         default: break;
         }
     }
     throw Error(CLEORA_E_INVAL, "no kernel variant for this embedding width");
+}
+
+// The column-blocked epilogues exist for single-graph launches only.
+template <typename T>
+void spmm_dispatch(const Variant &v, const StepDesc *host, const StepDesc *descs, int n_desc,
+                   int64_t waves, int32_t persist, hipStream_t s)
+{
+    if (host && (host->row_scale || host->row_ss))
+        spmm_dispatch_ext<T, true>(v, host, descs, n_desc, waves, persist, s);
+    else
+        spmm_dispatch_ext<T, false>(v, host, descs, n_desc, waves, persist, s);
 }
 
 template <typename T, int VPLF>
@@ -707,17 +746,18 @@ void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t
 
 void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const int64_t *row0,
                  const uint64_t *seeds, int n_graphs, uint64_t seed0, hipStream_t s,
-                 const int32_t *ids, int64_t max_blocks)
+                 const int32_t *ids, int64_t max_blocks, int32_t dfull, int32_t j0)
 {
+    if (dfull <= 0) dfull = dim;
     const int epv = dtype == CLEORA_BF16 ? 8 : 4;
     const int64_t total = n * (ld / epv);
     const unsigned g = grid_for(total, 256, max_blocks > 0 ? max_blocks : 1 << 16);
     if (dtype == CLEORA_BF16)
         k_init<uint16_t><<<g, 256, 0, s>>>(reinterpret_cast<uint16_t *>(E), n, dim, ld, row0,
-                                           seeds, n_graphs, seed0, ids);
+                                           seeds, n_graphs, seed0, ids, dfull, j0);
     else
         k_init<float><<<g, 256, 0, s>>>(reinterpret_cast<float *>(E), n, dim, ld, row0, seeds,
-                                        n_graphs, seed0, ids);
+                                        n_graphs, seed0, ids, dfull, j0);
     CLEORA_LAUNCH_CHECK();
 }
 

@@ -552,6 +552,29 @@ int cleora_propagate(cleora_ctx *c, int32_t k, void *stream)
     ABI_END
 }
 
+int cleora_embed_blocked(cleora_ctx *c, int32_t dim, int32_t block, int32_t dtype, uint64_t seed,
+                         int32_t k, void *out, int64_t ld_out, void *stream)
+{
+    ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_embed_blocked");
+    if (!c || !out) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (!c->has_graph) return fail(CLEORA_E_STATE, "no graph: call cleora_build_csr first");
+    check_dim(dim, dtype);
+    if (block < 1) return fail(CLEORA_E_INVAL, "block must be >= 1");
+    if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
+    if (ld_out < dim) return fail(CLEORA_E_INVAL, "ld_out < dim");
+    DeviceGuard g(c->device);
+    hipStream_t s = cleora::as_stream(stream);
+    const int32_t bw = std::min(block, dim);
+    // block buffers and the schedule for the widest block; no embedding
+    // remains afterwards
+    alloc_embedding(c, c->n, bw, dtype);
+    plan_embedding(c, s);
+    cleora::embed_blocked(c, dim, bw, dtype, seed, k, out, ld_out, s);
+    return CLEORA_OK;
+    ABI_END
+}
+
 int cleora_get_embedding(cleora_ctx *c, void *dst, int64_t ld, int32_t dst_dtype, void *stream)
 {
     ABI_BEGIN
