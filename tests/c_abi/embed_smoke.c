@@ -5,8 +5,10 @@
  *
  * Graph: n = 97 nodes, edges (i, i+1 mod n) and (i, 7i+3 mod n), loops
  * skipped; d = 16, k = 3, seed 42, float32.
- * Output: "n d" on the first line, then n lines of d values; the last line
- * is "bad_input <code> <message>".
+ * Output: "n d" on the first line, then n lines of d values, then
+ * "blocked_maxdiff <x>": the largest difference between that result and the
+ * same embedding computed 5 columns at a time into host memory
+ * (cleora_embed_blocked); the last line is "bad_input <code> <message>".
  */
 #include <stdio.h>
 #include <stdlib.h>
@@ -64,6 +66,16 @@ int main(void)
         for (int j = 0; j < D; ++j) printf(j ? " %.9g" : "%.9g", out[i * D + j]);
         printf("\n");
     }
+
+    /* the column-blocked form, straight into (pageable) host memory */
+    static float blk[N * D];
+    CK(cleora_embed_blocked(ctx, D, 5, CLEORA_F32, 42, K, blk, D, NULL));
+    double maxdiff = 0.0;
+    for (int i = 0; i < N * D; ++i) {
+        const double e = blk[i] > out[i] ? blk[i] - out[i] : out[i] - blk[i];
+        if (e > maxdiff) maxdiff = e;
+    }
+    printf("blocked_maxdiff %.9g\n", maxdiff);
 
     /* an id outside [0, N) */
     dst[5] = N;

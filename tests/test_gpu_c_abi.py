@@ -1,7 +1,7 @@
 """The C ABI from a plain C program (gcc; no Python or torch in the
 process): a small graph embedded through include/cleora.h matches the FP64
-oracle, and an edge id out of range comes back as CLEORA_E_INPUT with a
-message."""
+oracle, the column-blocked form of the same embedding agrees with it, and
+an edge id out of range comes back as CLEORA_E_INPUT with a message."""
 
 import os
 import subprocess
@@ -42,5 +42,7 @@ def test_c_program_matches_oracle():
     err = float(np.abs(got - want).max())
     print(f"C program: max-abs {err:.3e}")
     assert err <= 1e-5
+    tag, diff = lines[1 + n].split()
+    assert tag == "blocked_maxdiff" and float(diff) <= 2e-6
     _, code, msg = lines[-1].split(" ", 2)
     assert int(code) == 5 and "outside" in msg
