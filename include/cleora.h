@@ -142,6 +142,17 @@ int cleora_propagate(cleora_ctx *ctx, int32_t k, void *stream);
 int cleora_embed_blocked(cleora_ctx *ctx, int32_t dim, int32_t block, int32_t dtype, uint64_t seed,
                          int32_t k, void *out, int64_t ld_out, void *stream);
 
+/* Free device memory the context keeps only for reuse by later calls: the
+ * CSR build's temporaries (about 40 bytes per stored entry) always, and,
+ * when the context holds no embedding (after cleora_embed_blocked, before
+ * the first init, after a failed one), its embedding, schedule and
+ * column-blocked buffers.  The graph (CSR, M values, degrees, a chunk's
+ * nodes) and a current embedding stay usable; later calls allocate again
+ * what they need.  Meant for graphs near the device's capacity, e.g.
+ * between cleora_build_csr and cleora_embed_blocked.  Waits for all work on
+ * the device.  Errors: E_INVAL (NULL), E_DEVICE. */
+int cleora_release_scratch(cleora_ctx *ctx);
+
 /* Copy the current N x dim embedding into dst (device or host memory; a
  * host destination should be pinned) with a row stride of ld elements
  * (ld >= dim).  dst_dtype must equal the context dtype, or be CLEORA_F32

@@ -181,6 +181,12 @@ class Context:
                                                   out.data_ptr(), out.stride(0), _stream(stream)))
         return out
 
+    def release_scratch(self) -> "Context":
+        """Free the build's temporaries (and the embedding buffers when the
+        context holds no embedding); the graph stays."""
+        _lib.check(self._lib.cleora_release_scratch(self._h))
+        return self
+
     def sync(self, stream=None) -> None:
         _lib.check(self._lib.cleora_sync(self._h, _stream(stream)))
 

@@ -24,7 +24,8 @@ _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_build_init",
-    "cleora_init", "cleora_propagate", "cleora_embed_blocked", "cleora_get_embedding",
+    "cleora_init", "cleora_propagate", "cleora_embed_blocked", "cleora_release_scratch",
+    "cleora_get_embedding",
     "cleora_embedding_ptr",
     "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
     "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
@@ -87,6 +88,7 @@ def load() -> ctypes.CDLL:
         "cleora_init": (ctypes.c_int, [p, i32, i32, u64, p]),
         "cleora_propagate": (ctypes.c_int, [p, i32, p]),
         "cleora_embed_blocked": (ctypes.c_int, [p, i32, i32, i32, u64, i32, p, i64, p]),
+        "cleora_release_scratch": (ctypes.c_int, [p]),
         "cleora_get_embedding": (ctypes.c_int, [p, p, i64, i32, p]),
         "cleora_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p), ctypes.POINTER(i64)]),
         "cleora_previous_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p),

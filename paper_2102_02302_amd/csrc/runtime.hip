@@ -442,11 +442,14 @@ void cleora_destroy(cleora_ctx *c)
     try {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        DevBuf *bufs[] = {&c->rp, &c->col, &c->val, &c->deg, &c->E[0], &c->E[1],
-                          &c->split_items, &c->bucket_row, &c->long_rows, &c->chunk_base,
-                          &c->partial, &c->desc, &c->chunk_ids, &c->chunk_occ, &c->t_local, &c->t_expand, &c->t_edges, &c->t_wts, &c->t_cnt, &c->t_off, &c->t_keys,
-                          &c->t_tmp, &c->t_head, &c->t_pos, &c->t_esum, &c->t_lists,
-                          &c->t_scan, &c->t_small, &c->multi_desc};
+        DevBuf *bufs[] = {&c->rp,          &c->col,         &c->val,        &c->deg,
+                          &c->E[0],        &c->E[1],        &c->split_items, &c->bucket_row,
+                          &c->long_rows,   &c->chunk_base,  &c->partial,    &c->desc,
+                          &c->blk_norms,   &c->chunk_ids,   &c->chunk_occ,  &c->t_local,
+                          &c->t_expand,    &c->t_edges,     &c->t_wts,      &c->t_cnt,
+                          &c->t_off,       &c->t_keys,      &c->t_tmp,      &c->t_head,
+                          &c->t_pos,       &c->t_esum,      &c->t_lists,    &c->t_scan,
+                          &c->t_small,     &c->multi_desc};
         drop_graphs(c);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
@@ -571,6 +574,30 @@ int cleora_embed_blocked(cleora_ctx *c, int32_t dim, int32_t block, int32_t dtyp
     alloc_embedding(c, c->n, bw, dtype);
     plan_embedding(c, s);
     cleora::embed_blocked(c, dim, bw, dtype, seed, k, out, ld_out, s);
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_release_scratch(cleora_ctx *c)
+{
+    ABI_BEGIN
+    cleora::TraceRange trace_range("cleora_release_scratch");
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    DeviceGuard g(c->device);
+    CLEORA_HIP(hipDeviceSynchronize());  // nothing in flight may still use them
+    // every user of these ensures them again before use (t_small stays: it
+    // carries the build's status words and is allocated at creation)
+    DevBuf *tmp[] = {&c->t_edges, &c->t_wts,  &c->t_cnt,   &c->t_off,   &c->t_keys,
+                     &c->t_tmp,   &c->t_head, &c->t_pos,   &c->t_esum,  &c->t_lists,
+                     &c->t_scan,  &c->t_local, &c->t_expand, &c->multi_desc};
+    for (DevBuf *b : tmp) b->release();
+    if (!c->has_emb) {
+        drop_graphs(c);  // captured iterations point at the buffers below
+        DevBuf *emb[] = {&c->E[0],      &c->E[1],       &c->split_items, &c->bucket_row,
+                         &c->long_rows, &c->chunk_base, &c->partial,     &c->desc,
+                         &c->blk_norms};
+        for (DevBuf *b : emb) b->release();
+    }
     return CLEORA_OK;
     ABI_END
 }

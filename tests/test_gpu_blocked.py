@@ -190,3 +190,32 @@ def test_errors_and_state(cl):
         assert e.value.code == _lib.E_STATE
         ctx.init(32, "f32", 1).propagate(2)  # the graph is still there
         assert np.abs(ctx.embedding().cpu().numpy() - out.cpu().numpy()).max() <= 2e-6
+
+
+def test_release_scratch(cl):
+    # the build's temporaries, and the block buffers once no embedding is
+    # held, go back to the device; the graph and a current embedding stay
+    import torch
+    from paper_2102_02302_amd import _lib
+    g = gen.chung_lu(200_000, 2_000_000, 2.1, 64)
+    free = lambda: torch.cuda.mem_get_info()[0]  # noqa: E731
+    with cl.Context(0) as ctx:
+        ctx.build_graph(g)
+        torch.cuda.synchronize()
+        f0 = free()
+        ctx.release_scratch()
+        f1 = free()
+        assert f1 - f0 >= 100 << 20, (f0, f1)  # about 40 bytes per stored entry
+        out = torch.empty((g.n, 96), device="cuda")
+        ctx.embed_blocked(96, 40, 3, "f32", 4, out=out)
+        f2 = free()
+        ctx.release_scratch()
+        assert free() - f2 >= 2 * g.n * 40 * 4, (f2, free())  # the two block buffers
+        ctx.init(96, "f32", 4).propagate(2)
+        ctx.release_scratch()  # keeps the embedding and its schedule
+        ctx.propagate(1)
+        ref = ctx.embedding()
+        assert float((out - ref).abs().max()) <= 2e-6
+        ctx.propagate(1)  # and it goes on propagating
+        assert ctx.info()["iteration"] == 4
+    assert _lib.load().cleora_release_scratch(None) == _lib.E_INVAL
