@@ -405,6 +405,8 @@ def parse():
                     help="er10k | chunglu1m | chunglu10m | bipartite6m")
     ap.add_argument("--dtype", default=None, help="override the workload's dtype (f32|bf16)")
     ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--dim", type=int, default=None,
+                    help="override the workload's d (e.g. one GPU's share of the columns)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -505,7 +507,7 @@ def main():
     import paper_2102_02302_amd as cl
 
     spec = gen.WORKLOADS[args.workload]
-    dim = spec["dim"]
+    dim = args.dim or spec["dim"]
     k = args.k if args.k is not None else spec["k"]
     dtype = args.dtype or spec["dtype"]
     esz = 2 if dtype == "bf16" else 4
@@ -587,7 +589,8 @@ def main():
     split_rows = sched["split_rows"]
     spmm_bytes = nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
-    traffic = _traffic(args.workload, dtype)
+    # the counter summaries are of the workload's own d
+    traffic = _traffic(args.workload, dtype) if dim == spec["dim"] else None
     iter_ms = spmm_ms + comb_ms
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
