@@ -401,7 +401,8 @@ typedef struct {
  * of admitted requests (0: 80% of the device memory free at creation);
  * builders: build threads; max_group: most requests built together (1:
  * every request on its own).  flags: CLEORA_DIRECTED / CLEORA_EMPTY_KEEP
- * for every request.  Errors: E_INVAL, E_DEVICE, E_NOMEM. */
+ * for every request.  Errors: E_INVAL (dim outside [1, CLEORA_MAX_DIM_*]
+ * for the dtype, other bad parameters), E_DEVICE, E_NOMEM. */
 int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t dtype, int32_t k,
                          int32_t slots, int64_t budget_bytes, int32_t builders, int32_t max_group,
                          uint32_t flags);
@@ -419,7 +420,9 @@ int cleora_server_stats(cleora_server *s, int64_t *steps, int64_t *stepped, int3
 /* Seconds since the server was created (the clock of the completions). */
 double cleora_server_now(cleora_server *s);
 /* Stops the threads (requests not yet completed are dropped) and frees
- * everything.  NULL is ignored. */
+ * everything.  No other call on the same server may be in progress or
+ * start afterwards (submit, poll and stats are thread-safe among
+ * themselves, not against destroy).  NULL is ignored. */
 void cleora_server_destroy(cleora_server *s);
 
 /* Message for the last error on this thread ("" if none). */

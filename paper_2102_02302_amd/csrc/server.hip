@@ -499,8 +499,9 @@ int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t d
         return CLEORA_E_INVAL;
     }
     *out = nullptr;
-    if (dim < 1 || (dtype != CLEORA_F32 && dtype != CLEORA_BF16) || k < 0 || slots < 1 ||
-        budget_bytes < 0 || builders < 1 || max_group < 1 ||
+    if (dim < 1 || (dtype != CLEORA_F32 && dtype != CLEORA_BF16) ||
+        dim > (dtype == CLEORA_BF16 ? CLEORA_MAX_DIM_BF16 : CLEORA_MAX_DIM_F32) || k < 0 ||
+        slots < 1 || budget_bytes < 0 || builders < 1 || max_group < 1 ||
         (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP))) {
         cleora::set_last_error("bad server parameters");
         return CLEORA_E_INVAL;

@@ -93,6 +93,8 @@ def test_more_error_paths_without_gpu(lib):
     assert lib.cleora_server_create(null, 0, 16, 0, 2, 2, 1 << 20, 1, 1, 0) == _lib.E_INVAL
     h = ctypes.c_void_p()
     for args in ((0, 0, 0, 2, 2, 1 << 20, 1, 1, 0),      # dim 0
+                 (0, 4097, 0, 2, 2, 1 << 20, 1, 1, 0),   # dim above the FP32 maximum
+                 (0, 8193, 1, 2, 2, 1 << 20, 1, 1, 0),   # dim above the BF16 maximum
                  (0, 16, 7, 2, 2, 1 << 20, 1, 1, 0),     # bad dtype
                  (0, 16, 0, -1, 2, 1 << 20, 1, 1, 0),    # k < 0
                  (0, 16, 0, 2, 0, 1 << 20, 1, 1, 0),     # no slots
