@@ -408,6 +408,8 @@ def parse():
     ap.add_argument("--dim", type=int, default=None,
                     help="override the workload's d (e.g. one GPU's share of the columns)")
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--slices", type=int, default=0,
+                    help="run each iteration as column slices this wide (FP32; 0: whole rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's schedule autotuner (run once per graph "
@@ -533,6 +535,8 @@ def main():
     ctx = cl.Context(0)
     if args.chunk:
         ctx.set_chunk(args.chunk)
+    if args.slices:
+        ctx.set_slices(args.slices)
 
     def step():
         # CSR build and T_0 in one call (T_0 written while the CSR is built)
@@ -582,19 +586,27 @@ def main():
     edge_dims = float(k) * nnz * dim
     value = edge_dims / (ms_per_step * 1e-3) / 1e9
 
-    # dominant kernel: fused SpMM + normalise
-    spmm_ms = kt["spmm_ms"] / max(kt["spmm_launches"], 1)
-    comb_ms = kt["combine_ms"] / max(kt["combine_launches"], 1) if kt["combine_launches"] else 0.0
+    # dominant kernel: fused SpMM + normalise; with column slices, the S
+    # slice launches of one iteration together (each re-reads col and val)
+    ld = -(-dim * esz // 16) * 16 // esz
+    n_slices = -(-ld // args.slices) if args.slices and dtype == "f32" else 1
+    spmm_ms = kt["spmm_ms"] / max(kt["spmm_launches"], 1) * n_slices
+    comb_ms = (kt["combine_ms"] / max(kt["combine_launches"], 1) * n_slices
+               if kt["combine_launches"] else 0.0)
     sched = ctx.schedule()
     split_rows = sched["split_rows"]
-    spmm_bytes = nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz
+    spmm_bytes = n_slices * nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     # the counter summaries are of the workload's own d
     traffic = _traffic(args.workload, dtype) if dim == spec["dim"] else None
-    iter_ms = spmm_ms + comb_ms
+    # with slices an iteration also zeroes, inverts and scales: take the
+    # separately timed propagate call instead of the SpMM launches
+    iter_ms = spmm_ms + comb_ms if n_slices == 1 else phase["propagate_ms"] / k
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_spmm_norm", "bytes_per_launch": int(spmm_bytes),
+                "kernel": "k_spmm_norm" if n_slices == 1 else
+                          f"k_spmm_norm, {n_slices} column slices per iteration (figures per iteration)",
+                "bytes_per_launch": int(spmm_bytes),
                 "avg_launch_ms": round(spmm_ms, 4), "launches": kt["spmm_launches"],
                 "combine_avg_ms": round(comb_ms, 4), "schedule": sched, "autotune": tuned}
 
@@ -614,6 +626,7 @@ def main():
         "config": {"workload": args.workload, "desc": spec["desc"], "n_nodes": n,
                    "n_edges": g.m, "nnz": nnz, "dim": dim, "k": k,
                    "step": "build CSR + FP64 row sums + init T_0 + k iterations",
+                   "column_slices": n_slices,
                    "parallelism": "single GPU"},
         "propagate_only": {"ms_per_iteration": round(iter_ms, 4),
                            "gedge_dims_per_s": round(nnz * dim / (iter_ms * 1e-3) / 1e9, 2),

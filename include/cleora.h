@@ -226,6 +226,23 @@ int cleora_sync(cleora_ctx *ctx, void *stream);
  * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 
+/* Run the iterations of the next cleora_init, cleora_build_init or
+ * cleora_embed_batch on this context as column slices `cols` wide (0, the
+ * default: whole rows).  Float32 embeddings only; a CLEORA_BF16 context
+ * ignores it.  Each slice's SpMM gathers that part of the neighbour rows
+ * (a narrower gather keeps more of the most-used rows of T in cache),
+ * stores its rows unscaled and adds its share of each row's squared norm;
+ * then every row is scaled by 1/norm (Section 3.2's normalisation, over
+ * the whole row), so T_t is complete after each iteration.  Results differ
+ * from whole rows in float32 rounding only (a narrow slice may gather
+ * several entries at once in lane groups, and each squared norm is summed
+ * slice by slice); with cols >= the padded row width (one slice) they are
+ * the same bits.  Propagate resumption, graph replay and batch = solo (with
+ * the same setting) hold as before.
+ * cleora_step_multi and cleora_propagate_rows use whole rows.
+ * Errors: E_INVAL (cols < 0, not a multiple of 4, or above 4096). */
+int cleora_set_slices(cleora_ctx *ctx, int32_t cols);
+
 /* Fix the propagation schedule instead of the autotuned or default one
  * (takes effect at the next cleora_init; cleora_autotune clears it).
  * pack: entries per work item for rows that are not split (0: automatic,

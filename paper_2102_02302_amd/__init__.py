@@ -144,6 +144,12 @@ class Context:
     def set_chunk(self, chunk: int) -> None:
         _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
 
+    def set_slices(self, cols: int) -> None:
+        """Run the iterations of the next init as column slices ``cols`` wide
+        (0: whole rows); float32 embeddings only (results differ from whole
+        rows in float32 rounding only)."""
+        _lib.check(self._lib.cleora_set_slices(self._h, int(cols)))
+
     def set_schedule(self, pack: int = 0, persistent: int = -1) -> None:
         """Fix the packing size (0: automatic) and SpMM grid (-1: automatic,
         0: one wave per item, m: m x the resident waves) for the next init."""

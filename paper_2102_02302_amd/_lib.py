@@ -29,6 +29,7 @@ EXPORTS = [
     "cleora_embedding_ptr",
     "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
     "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
+    "cleora_set_slices",
     "cleora_set_timing",
     "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star",
     "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
@@ -89,6 +90,7 @@ def load() -> ctypes.CDLL:
         "cleora_propagate": (ctypes.c_int, [p, i32, p]),
         "cleora_embed_blocked": (ctypes.c_int, [p, i32, i32, i32, u64, i32, p, i64, p]),
         "cleora_release_scratch": (ctypes.c_int, [p]),
+        "cleora_set_slices": (ctypes.c_int, [p, i32]),
         "cleora_get_embedding": (ctypes.c_int, [p, p, i64, i32, p]),
         "cleora_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p), ctypes.POINTER(i64)]),
         "cleora_previous_embedding_ptr": (ctypes.c_int, [p, ctypes.POINTER(p),

@@ -40,7 +40,61 @@ __global__ void k_inv_norm(int64_t n, const float *__restrict__ ss, float *__res
     }
 }
 
+__global__ void k_fill_zero(int64_t n, float *__restrict__ x)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0f;
+}
+
+// One wave per row: the row's float4 vectors times its factor (the fused
+// kernel's `acc * inv`, applied to the stored unscaled row).
+__global__ void k_scale_rows(float4 *__restrict__ E, int64_t n, int32_t vpr,
+                             const float *__restrict__ inv)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n;
+         r += waves) {
+        const float f = inv[r];
+        float4 *row = E + r * vpr;
+        for (int32_t j = lane; j < vpr; j += 64) {
+            float4 x = row[j];
+            x.x *= f;
+            x.y *= f;
+            x.z *= f;
+            x.w *= f;
+            row[j] = x;
+        }
+    }
+}
+
+unsigned grid_for_rows(int64_t n, int per_block)
+{
+    return (unsigned)std::min<int64_t>(std::max<int64_t>((n + per_block - 1) / per_block, 1),
+                                       65536);
+}
+
 }  // namespace
+
+void launch_fill_zero(float *x, int64_t n, hipStream_t s)
+{
+    k_fill_zero<<<grid_for_rows(n, 256), 256, 0, s>>>(n, x);
+    CLEORA_LAUNCH_CHECK();
+}
+
+void launch_inv_norm(const float *ss, float *inv, int64_t n, hipStream_t s)
+{
+    k_inv_norm<<<grid_for_rows(n, 256), 256, 0, s>>>(n, ss, inv);
+    CLEORA_LAUNCH_CHECK();
+}
+
+void launch_scale_rows(float *E, int64_t n, int32_t ld, const float *inv, hipStream_t s)
+{
+    k_scale_rows<<<grid_for_rows(n, 4), 256, 0, s>>>(reinterpret_cast<float4 *>(E), n, ld / 4,
+                                                     inv);
+    CLEORA_LAUNCH_CHECK();
+}
 
 void embed_blocked(cleora_ctx *c, int32_t dim, int32_t block, int32_t dtype, uint64_t seed,
                    int32_t k, void *out, int64_t ld_out, hipStream_t s)

@@ -60,12 +60,14 @@ struct StepDesc {
     int32_t chunk;
     uint32_t flags;
     int32_t persist;  // SpMM grid: 0 = one wave per item, m > 0 = m x the resident blocks
-    // Column-blocked form (both null otherwise, and in multi-context
+    // Column blocks and slices (both null otherwise, and in multi-context
     // launches): with row_ss, each row's squared norm is added to
-    // row_ss[r] and nothing is stored; with row_scale, row r is scaled by
-    // row_scale[r] instead of being normalised.
+    // row_ss[r] and the row is stored unscaled if keep_rows, else not at
+    // all; with row_scale, row r is scaled by row_scale[r] instead of being
+    // normalised.
     const float *row_scale;
     float *row_ss;
+    int32_t keep_rows;
 };
 
 // Kernel variant for an embedding layout.
@@ -84,8 +86,9 @@ void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s);
 // Several contexts: `descs` is a device table with wave_begin prefixes.
 void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
                        int32_t persist, hipStream_t s);
-// One-time set-up of a persistent SpMM grid for this variant (no launch).
-void prime_spmm(const Variant &v, int32_t persist);
+// One-time set-up of a persistent SpMM grid for this variant (no launch);
+// ext: the instantiation with the column-block epilogues.
+void prime_spmm(const Variant &v, int32_t persist, bool ext = false);
 void launch_combine(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_blocks,
                     hipStream_t s);
 // T_0 for rows of one or more graphs (row0[g]..row0[g+1] use seeds[g] and
@@ -119,6 +122,12 @@ void launch_merge_finish(const float *acc, int64_t ld_acc, const float *wsum, in
 void launch_widen_bf16(const void *src, int64_t n, int32_t dim, int32_t ld_src, float *dst,
                        int64_t ld_dst, hipStream_t s);
 
+// Row-norm helpers of column slices (blocked.hip): x = 0; inv = 1/sqrt(ss)
+// (0 for a zero row); row r of the n x ld float32 matrix E times inv[r].
+void launch_fill_zero(float *x, int64_t n, hipStream_t s);
+void launch_inv_norm(const float *ss, float *inv, int64_t n, hipStream_t s);
+void launch_scale_rows(float *E, int64_t n, int32_t ld, const float *inv, hipStream_t s);
+
 }  // namespace cleora
 
 // ------------------------------------------------------------------- ctx
@@ -148,6 +157,11 @@ struct cleora_ctx {
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
     // column-blocked form: per-row 1/norm of iterations 1..k, squared norms
     cleora::DevBuf blk_norms;
+    // column slices of one iteration (FP32 only; 0: whole rows): requested
+    // width, width in use, the slices' combine descriptors, squared norms
+    // and 1/norm per row
+    int32_t slice_req = 0, slice_cols = 0;
+    cleora::DevBuf slice_desc, slice_norms;
 
     // build temporaries (grow-only)
     cleora::DevBuf t_edges, t_wts, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
@@ -184,6 +198,9 @@ int32_t tuned_persist(const cleora_ctx *c);
 // Fill the two per-parity step descriptors of a context.
 void write_descs(cleora_ctx *c, hipStream_t s);
 StepDesc host_desc(const cleora_ctx *c, int parity);
+// Column slice starting at column c0 (slice_cols wide, or to ld) of
+// buffer `parity`: unscaled rows out, squared norms added to slice_norms.
+StepDesc slice_desc(const cleora_ctx *c, int parity, int32_t c0);
 // runtime.hip helpers shared with the server
 void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s);
 // Several graphs as one block-diagonal graph: their edges concatenated in

@@ -19,12 +19,14 @@
 // sums are float32 FMAs; the row norm is a wave reduction in the epilogue,
 // so T_t is written once and never re-read by this iteration.
 //
-// Column-blocked form.  Columns of T interact only through the row norms,
-// so an embedding too wide for device memory is propagated a block of
-// columns at a time.  For that the SpMM has two more epilogues (template
-// flag EXT): add the block's share of each row's squared norm to a vector
-// (no store), or scale each row by a given factor (1/norm of the whole row)
-// instead of normalising it.
+// Column blocks and slices.  Columns of T interact only through the row
+// norms, so a block of columns can be propagated on its own once the norms
+// are known (an embedding too wide for device memory), and one iteration
+// can run as column slices of the resident rows (narrower gathers keep more
+// of the hot rows in cache).  For both the SpMM has more epilogues
+// (template flag EXT): add the slice's share of each row's squared norm to
+// a vector, storing nothing or the unscaled row; or scale each row by a
+// given factor (1/norm of the whole row) instead of normalising it.
 #include "internal.hpp"
 
 #include <algorithm>
@@ -327,9 +329,10 @@ __device__ __forceinline__ void reduce_groups(float (&acc)[VPL][EPV])
 
 // One wave's work item of the fused SpMM + normalise step: either a chunk
 // of a split row (partial sum to `partial`) or a packed group of rows
-// (normalised rows to Eout).  With EXT, the column-blocked epilogues: a
-// non-null row_ss receives each row's squared norm (added, nothing
-// stored), else row r is scaled by row_scale[r].
+// (normalised rows to Eout).  With EXT, the column-block epilogues: a
+// non-null row_ss receives each row's squared norm (added; the row itself
+// is stored unscaled when keep_rows, else not at all), else row r is
+// scaled by row_scale[r].
 template <typename T, int G, int VPL, int U, bool EXT>
 __device__ __forceinline__ void spmm_item(
     int64_t wave, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
@@ -337,7 +340,7 @@ __device__ __forceinline__ void spmm_item(
     float *__restrict__ partial, const int2 *__restrict__ split_items,
     const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
     int chunk, uint32_t flags, int cpr, const float *__restrict__ row_scale,
-    float *__restrict__ row_ss)
+    float *__restrict__ row_ss, int keep_rows)
 {
     constexpr int EPV = EmbT<T>::EPV;
     constexpr int LPG = WAVE / G;
@@ -406,9 +409,11 @@ __device__ __forceinline__ void spmm_item(
             if (row_ss) {
                 // every group holds the whole row's sum after reduce_groups
                 if (lane == 0) row_ss[r] += ss;
-                continue;
+                if (!keep_rows) continue;
+                inv = 1.0f;  // the row's norm is known after its last slice
+            } else {
+                inv = row_scale[r];
             }
-            inv = row_scale[r];
         } else {
             inv = ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f;
         }
@@ -447,13 +452,13 @@ __global__ __launch_bounds__(256) void k_spmm_norm(
     float *__restrict__ partial, const int2 *__restrict__ split_items,
     const int32_t *__restrict__ bucket_row, int64_t n_split, int64_t n_buckets, int ld,
     int chunk, uint32_t flags, int cpr, const float *__restrict__ row_scale,
-    float *__restrict__ row_ss)
+    float *__restrict__ row_ss, int keep_rows)
 {
     const int64_t items = n_split + n_buckets, stride = (int64_t)gridDim.x * 4;
     for (int64_t w = wave_id(); w < items; w += stride)
         spmm_item<T, G, VPL, U, EXT>(w, rp, col, val, Ein, Eout, partial, split_items,
                                      bucket_row, n_split, n_buckets, ld, chunk, flags, cpr,
-                                     row_scale, row_ss);
+                                     row_scale, row_ss, keep_rows);
 }
 
 // Several graphs (continuous batching): each item's graph is found in the
@@ -469,7 +474,7 @@ __global__ __launch_bounds__(256) void k_spmm_norm_multi(const StepDesc *__restr
                                        reinterpret_cast<const uint4 *>(D.Ein),
                                        reinterpret_cast<uint4 *>(D.Eout), D.partial,
                                        D.split_items, D.bucket_row, D.n_split, D.n_buckets, D.ld,
-                                       D.chunk, D.flags, cpr, nullptr, nullptr);
+                                       D.chunk, D.flags, cpr, nullptr, nullptr, 0);
     }
 }
 
@@ -556,11 +561,14 @@ __global__ __launch_bounds__(WPB * 64) void k_combine(const StepDesc *__restrict
         ss = fmaf(acc[v].w, acc[v].w, ss);
     }
     ss = wave_sum(ss);
-    if (D.row_ss) {  // column-blocked form: the squared norm only
+    float inv;
+    if (D.row_ss) {  // column blocks and slices: the squared norm, the row unscaled
         if (lane == 0) D.row_ss[row] += ss;
-        return;
+        if (!D.keep_rows) return;
+        inv = 1.0f;
+    } else {
+        inv = D.row_scale ? D.row_scale[row] : (ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f);
     }
-    const float inv = D.row_scale ? D.row_scale[row] : (ss > 0.0f ? 1.0f / sqrtf(ss) : 0.0f);
 #pragma unroll
     for (int v = 0; v < VPLF; ++v) {
         const int ch = lane + v * 64;
@@ -614,7 +622,7 @@ void spmm_launch(const StepDesc *host, const StepDesc *descs, int n_desc, int64_
         k_spmm_norm<T, G, VPL, U, EXT><<<(unsigned)blocks, 256, 0, s>>>(
             D.rp, D.col, D.val, reinterpret_cast<const uint4 *>(D.Ein),
             reinterpret_cast<uint4 *>(D.Eout), D.partial, D.split_items, D.bucket_row, D.n_split,
-            D.n_buckets, D.ld, D.chunk, D.flags, cpr, D.row_scale, D.row_ss);
+            D.n_buckets, D.ld, D.chunk, D.flags, cpr, D.row_scale, D.row_ss, D.keep_rows);
     } else {
         k_spmm_norm_multi<T, G, VPL, U><<<(unsigned)blocks, 256, 0, s>>>(descs, n_desc, waves,
                                                                          cpr);
@@ -721,12 +729,17 @@ void launch_spmm(const Variant &v, const StepDesc &one, hipStream_t s)
 
 // Runs the one-time occupancy queries of a persistent grid now, so that
 // none happens inside a graph capture (no kernel is launched).
-void prime_spmm(const Variant &v, int32_t persist)
+void prime_spmm(const Variant &v, int32_t persist, bool ext)
 {
     if (persist <= 0) return;
     StepDesc none{};
-    if (v.dtype == CLEORA_BF16) spmm_dispatch<uint16_t>(v, &none, nullptr, 1, 0, persist, nullptr);
-    else spmm_dispatch<float>(v, &none, nullptr, 1, 0, persist, nullptr);
+    if (v.dtype == CLEORA_BF16) {
+        if (ext) spmm_dispatch_ext<uint16_t, true>(v, &none, nullptr, 1, 0, persist, nullptr);
+        else spmm_dispatch_ext<uint16_t, false>(v, &none, nullptr, 1, 0, persist, nullptr);
+    } else {
+        if (ext) spmm_dispatch_ext<float, true>(v, &none, nullptr, 1, 0, persist, nullptr);
+        else spmm_dispatch_ext<float, false>(v, &none, nullptr, 1, 0, persist, nullptr);
+    }
 }
 
 void launch_spmm_multi(const Variant &v, const StepDesc *descs, int n_desc, int64_t total_waves,
@@ -846,7 +859,33 @@ void write_descs(cleora_ctx *c, hipStream_t s)
     StepDesc h[2] = {host_desc(c, 0), host_desc(c, 1)};
     c->desc.ensure(sizeof(h));
     CLEORA_HIP(hipMemcpyAsync(c->desc.p, h, sizeof(h), hipMemcpyHostToDevice, s));
+    std::vector<StepDesc> sl;
+    if (c->slice_cols > 0) {
+        // column slices: entry p * S + j reads buffer p, columns of slice j
+        c->slice_norms.ensure(2 * sizeof(float) * (size_t)std::max<int64_t>(c->n, 1));
+        for (int p = 0; p < 2; ++p)
+            for (int32_t c0 = 0; c0 < c->ld; c0 += c->slice_cols) {
+                sl.push_back(slice_desc(c, p, c0));
+                // a persistent grid's occupancy query, outside any capture
+                if (p == 0)
+                    prime_spmm(choose_variant(CLEORA_F32, std::min(c->slice_cols, c->ld - c0)),
+                               c->persist, true);
+            }
+        c->slice_desc.ensure(sizeof(StepDesc) * sl.size());
+        CLEORA_HIP(hipMemcpyAsync(c->slice_desc.p, sl.data(), sizeof(StepDesc) * sl.size(),
+                                  hipMemcpyHostToDevice, s));
+    }
     CLEORA_HIP(hipStreamSynchronize(s));
+}
+
+StepDesc slice_desc(const cleora_ctx *c, int parity, int32_t c0)
+{
+    StepDesc d = host_desc(c, parity);  // the row stride stays ld
+    d.Ein = static_cast<const float *>(d.Ein) + c0;
+    d.Eout = static_cast<float *>(d.Eout) + c0;
+    d.row_ss = c->slice_norms.as<float>();
+    d.keep_rows = 1;
+    return d;
 }
 
 }  // namespace cleora

@@ -146,35 +146,67 @@ hipEvent_t take_event(cleora_ctx *c)
     return e;
 }
 
-// Queue k iterations starting from buffer parity `cur` (no state change).
-void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
+// One spmm (+ combine) launch of enqueue_steps, with timing events when on.
+void launch_step(cleora_ctx *c, const cleora::Variant &v, const StepDesc &d,
+                 const StepDesc *dev_desc, hipStream_t s)
 {
-    const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
-    for (int32_t t = 0; t < k; ++t) {
-        const StepDesc d = cleora::host_desc(c, cur);
-        hipEvent_t a = nullptr, b = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
+        CLEORA_HIP(hipEventRecord(a, s));
+    }
+    cleora::launch_spmm(v, d, s);
+    if (c->timing) {
+        CLEORA_HIP(hipEventRecord(b, s));
+        c->ev_spmm.emplace_back(a, b);
+    }
+    if (c->n_long > 0) {
         if (c->timing) {
             a = take_event(c);
             b = take_event(c);
             CLEORA_HIP(hipEventRecord(a, s));
         }
-        cleora::launch_spmm(v, d, s);
+        cleora::launch_combine(v, dev_desc, 1, c->n_long, s);
         if (c->timing) {
             CLEORA_HIP(hipEventRecord(b, s));
-            c->ev_spmm.emplace_back(a, b);
+            c->ev_comb.emplace_back(a, b);
         }
-        if (c->n_long > 0) {
-            if (c->timing) {
-                a = take_event(c);
-                b = take_event(c);
-                CLEORA_HIP(hipEventRecord(a, s));
-            }
-            cleora::launch_combine(v, c->desc.as<StepDesc>() + cur, 1, c->n_long, s);
-            if (c->timing) {
-                CLEORA_HIP(hipEventRecord(b, s));
-                c->ev_comb.emplace_back(a, b);
-            }
+    }
+}
+
+// k iterations as column slices (FP32): every slice stores its rows
+// unscaled and adds its squared norms; then 1/norm per row and one pass
+// that scales the rows, so T_t is complete after every iteration.
+// (Applying the factors inside the next iteration's gather instead, and
+// scaling only at the end, was slower: each entry then also reads its
+// neighbour's factor from an N-long vector.)
+void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
+{
+    const int64_t n = c->n;
+    const int32_t B = c->slice_cols, S = (c->ld + B - 1) / B;
+    float *ss = c->slice_norms.as<float>(), *inv = ss + n;
+    for (int32_t t = 0; t < k; ++t) {
+        cleora::launch_fill_zero(ss, n, s);
+        for (int32_t j = 0; j < S; ++j) {
+            const int32_t c0 = j * B;
+            const cleora::Variant v = cleora::choose_variant(CLEORA_F32, std::min(B, c->ld - c0));
+            launch_step(c, v, cleora::slice_desc(c, cur, c0),
+                        c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s);
         }
+        cleora::launch_inv_norm(ss, inv, n, s);
+        cleora::launch_scale_rows(c->E[cur ^ 1].as<float>(), n, c->ld, inv, s);
+        cur ^= 1;
+    }
+}
+
+// Queue k iterations starting from buffer parity `cur` (no state change).
+void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
+{
+    if (c->slice_cols > 0) return enqueue_sliced_steps(c, k, cur, s);
+    const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
+    for (int32_t t = 0; t < k; ++t) {
+        launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
         cur ^= 1;
     }
 }
@@ -239,6 +271,7 @@ void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
     c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
+    c->slice_cols = dtype == CLEORA_F32 ? c->slice_req : 0;
     const size_t ebytes = (size_t)n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
@@ -449,7 +482,7 @@ void cleora_destroy(cleora_ctx *c)
                           &c->t_expand,    &c->t_edges,     &c->t_wts,      &c->t_cnt,
                           &c->t_off,       &c->t_keys,      &c->t_tmp,      &c->t_head,
                           &c->t_pos,       &c->t_esum,      &c->t_lists,    &c->t_scan,
-                          &c->t_small,     &c->multi_desc};
+                          &c->t_small,     &c->multi_desc,  &c->slice_desc, &c->slice_norms};
         drop_graphs(c);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
@@ -572,6 +605,7 @@ int cleora_embed_blocked(cleora_ctx *c, int32_t dim, int32_t block, int32_t dtyp
     // block buffers and the schedule for the widest block; no embedding
     // remains afterwards
     alloc_embedding(c, c->n, bw, dtype);
+    c->slice_cols = 0;  // blocks are propagated whole
     plan_embedding(c, s);
     cleora::embed_blocked(c, dim, bw, dtype, seed, k, out, ld_out, s);
     return CLEORA_OK;
@@ -595,7 +629,7 @@ int cleora_release_scratch(cleora_ctx *c)
         drop_graphs(c);  // captured iterations point at the buffers below
         DevBuf *emb[] = {&c->E[0],      &c->E[1],       &c->split_items, &c->bucket_row,
                          &c->long_rows, &c->chunk_base, &c->partial,     &c->desc,
-                         &c->blk_norms};
+                         &c->blk_norms, &c->slice_desc, &c->slice_norms};
         for (DevBuf *b : emb) b->release();
     }
     return CLEORA_OK;
@@ -761,6 +795,17 @@ int cleora_set_chunk(cleora_ctx *c, int32_t chunk)
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     if (chunk < 0 || chunk > (1 << 20)) return fail(CLEORA_E_INVAL, "chunk out of range");
     c->chunk_req = chunk;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_set_slices(cleora_ctx *c, int32_t cols)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (cols < 0 || (cols > 0 && (cols % 4 != 0 || cols > CLEORA_MAX_DIM_F32)))
+        return fail(CLEORA_E_INVAL, "cols must be 0 or a multiple of 4 up to 4096");
+    c->slice_req = cols;
     return CLEORA_OK;
     ABI_END
 }
