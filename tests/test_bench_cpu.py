@@ -97,3 +97,30 @@ def test_cpu_baseline_on_a_small_graph():
     r = bench._cpu_baseline(g, 16, 2)
     assert r["kind"] == "oracle" and r["unit"] == "GEdge-dims/s" and r["value"] > 0
     assert r["cores"] >= 1 and r["single_thread"]["value"] > 0
+
+
+def test_traffic_only_while_the_kernel_source_matches(tmp_path, monkeypatch):
+    # the committed counter summaries are of the current SpMM source
+    for dt in ("f32", "bf16"):
+        t = bench._traffic("chunglu1m", dt)
+        assert t is not None and t > 0, dt
+    # a summary of another source is not used
+    stale = tmp_path / "spmm_norm_chunglu1m_f32_pmc.json"
+    stale.write_text(json.dumps({"kernel_source_sha256_16": "0" * 16,
+                                 "hbm_bytes_per_launch": 1.0}))
+    monkeypatch.setattr(bench, "PMC_SUMMARY", str(tmp_path / "spmm_norm_{workload}_{dtype}_pmc.json"))
+    assert bench._traffic("chunglu1m", "f32") is None
+    stale.write_text(json.dumps({"kernel_source_sha256_16": bench.kernel_source_hash(),
+                                 "hbm_bytes_per_launch": 5.0}))
+    assert bench._traffic("chunglu1m", "f32") == 5.0
+    assert bench._traffic("chunglu10m", "f32") is None  # no summary for that workload
+
+
+def test_every_trace_summary_is_of_the_current_source():
+    # profiles/ holds one source's figures: each summary names the hash
+    prof = os.path.join(ROOT, "profiles")
+    h = bench.kernel_source_hash()
+    for name in sorted(os.listdir(prof)):
+        text = open(os.path.join(prof, name)).read()
+        if name.endswith("_trace.txt") or name.endswith(".json"):
+            assert h in text, name
