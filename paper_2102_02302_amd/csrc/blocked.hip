@@ -20,6 +20,9 @@
 // step for step (the squared norm is added to zero, 1/sqrt is taken with
 // the same expression, and the product with the row is the same), so the
 // result is bit-identical to it.
+//
+// The same row-norm helpers (zeroing, 1/sqrt, scaling rows) serve the
+// column-slice option of ordinary iterations, whose loop is in the runtime.
 #include "internal.hpp"
 
 #include <algorithm>
