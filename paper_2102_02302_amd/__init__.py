@@ -336,11 +336,14 @@ class Context:
 
 
 def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
-          empty_keep: bool = False, chunk: int = 0):
-    """Whole path for one graph: build M, initialise T_0, k iterations."""
+          empty_keep: bool = False, chunk: int = 0, slices: int = 0):
+    """Whole path for one graph: build M, initialise T_0, k iterations
+    (``slices``: the column-slice option of float32 iterations, 0 = off)."""
     with Context(device) as ctx:
         if chunk:
             ctx.set_chunk(chunk)
+        if slices:
+            ctx.set_slices(slices)
         ctx.build_graph_init(g, dim, dtype, seed, empty_keep=empty_keep)
         ctx.propagate(k)
         return ctx.embedding()
