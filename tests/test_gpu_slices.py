@@ -150,3 +150,9 @@ def test_set_slices_rejects_bad_values(cl):
             assert e.value.code == _lib.E_INVAL
         ctx.set_slices(0)
         ctx.set_slices(4096)
+
+
+def test_embed_with_slices(cl):
+    g = graphs()[0]
+    got = cl.embed(g, 256, 3, 4, slices=64).cpu().numpy()
+    assert np.array_equal(got, run(cl, g, 256, 3, 4, 64))
