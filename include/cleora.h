@@ -364,6 +364,17 @@ int cleora_embed_batch(cleora_ctx *ctx, int32_t n_graphs, const cleora_graph *gr
                        uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
                        void *stream);
 
+/* Per-graph status of the last cleora_embed_batch call on this context
+ * (n_graphs entries into host memory `status`): after a call that failed
+ * with E_INPUT, CLEORA_E_INPUT for each graph with an id outside [0,
+ * n_nodes) or a weight that is not finite and positive (found by a host
+ * check of the edge arrays), CLEORA_OK for the others, which can be
+ * submitted again without the bad ones; after a call that failed with
+ * another error, that code for every graph; after a successful call,
+ * CLEORA_OK for every graph.  Errors: E_INVAL (NULL, n_graphs not the last
+ * call's count), E_STATE (no batch call yet). */
+int cleora_batch_status(cleora_ctx *ctx, int32_t n_graphs, int32_t *status);
+
 /* Continuous batching: advance each of n contexts (each with an embedding,
  * all with the same dim and dtype) by ONE iteration, every context's rows
  * in the same kernel launches.  Each context's result is bit-identical to

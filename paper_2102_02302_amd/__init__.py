@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 from . import _lib
 from ._lib import BF16, DIRECTED, EMPTY_KEEP, F32, CleoraError, load  # noqa: F401
 
-__all__ = ["Context", "embed", "embed_batch", "embed_blocked", "embed_chunked",
+__all__ = ["Context", "embed", "embed_batch", "batch_status", "embed_blocked", "embed_chunked",
            "embed_new_nodes", "step_multi",
            "footprint_bytes", "CleoraError",
            "F32", "BF16", "DIRECTED", "EMPTY_KEEP", "load"]
@@ -426,6 +426,14 @@ def embed_batch(ctx: Context, graphs: Sequence, dim: int, k: int, seeds: Sequenc
     _lib.check(ctx._lib.cleora_embed_batch(ctx.handle, len(graphs), arr, flags, dim, code, k,
                                            out_ptrs, _stream(stream)))
     return outs
+
+
+def batch_status(ctx: Context, n_graphs: int) -> List[int]:
+    """Per-graph status codes of the last embed_batch call on ``ctx`` (after
+    a failure with E_INPUT, E_INPUT marks the graphs with bad edges)."""
+    arr = (ctypes.c_int32 * int(n_graphs))()
+    _lib.check(ctx._lib.cleora_batch_status(ctx.handle, int(n_graphs), arr))
+    return list(arr)
 
 
 def step_multi(ctxs: Sequence[Context], stream=None) -> None:

@@ -33,7 +33,8 @@ EXPORTS = [
     "cleora_set_timing",
     "cleora_kernel_time", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star",
     "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
-    "cleora_embed_batch", "cleora_step_multi", "cleora_server_create", "cleora_server_submit",
+    "cleora_embed_batch", "cleora_batch_status", "cleora_step_multi", "cleora_server_create",
+    "cleora_server_submit",
     "cleora_server_poll", "cleora_server_stats", "cleora_server_now", "cleora_server_destroy",
     "cleora_last_error",
 ]
@@ -121,6 +122,7 @@ def load() -> ctypes.CDLL:
         "cleora_chunk_info": (ctypes.c_int, [p, ctypes.POINTER(i64), p, p, p]),
         "cleora_merge_chunk": (ctypes.c_int, [p, p, i64, p, p]),
         "cleora_merge_finish": (ctypes.c_int, [ctypes.c_int, p, i64, p, i64, i32, p, i64, i32, p]),
+        "cleora_batch_status": (ctypes.c_int, [p, i32, p]),
         "cleora_embed_batch": (ctypes.c_int, [p, i32, ctypes.POINTER(Graph), u32, i32, i32, i32,
                                               ctypes.POINTER(p), p]),
         "cleora_step_multi": (ctypes.c_int, [ctypes.POINTER(p), i32, p]),

@@ -168,6 +168,9 @@ struct cleora_ctx {
         t_scan, t_small, multi_desc;
     int64_t *h_small = nullptr;  // pinned host mirror of t_small
 
+    // per-graph status of the last cleora_embed_batch call
+    std::vector<int32_t> batch_status;
+
     // captured k-iteration graphs, keyed by (k, starting parity)
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
     hipStream_t cap_stream = nullptr;

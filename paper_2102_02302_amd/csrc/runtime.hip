@@ -1067,6 +1067,44 @@ int cleora_merge_finish(int device, const float *acc, int64_t ld_acc, const floa
     ABI_END
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host check of one graph's edges (the error path of a batch only): ids in
+// [0, n), weights finite and positive, as the build's key kernel requires.
+int32_t graph_status(const cleora_graph &G)
+{
+    const int64_t m = G.n_edges;
+    if (m <= 0) return CLEORA_OK;
+    std::vector<int32_t> ids(2 * (size_t)m);
+    if (hipMemcpy(ids.data(), G.src, 4 * (size_t)m, hipMemcpyDefault) != hipSuccess ||
+        hipMemcpy(ids.data() + m, G.dst, 4 * (size_t)m, hipMemcpyDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return CLEORA_E_DEVICE;
+    }
+    for (int32_t id : ids)
+        if (id < 0 || id >= G.n_nodes) return CLEORA_E_INPUT;
+    if (G.w) {
+        std::vector<float> w((size_t)m);
+        if (hipMemcpy(w.data(), G.w, 4 * (size_t)m, hipMemcpyDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return CLEORA_E_DEVICE;
+        }
+        for (float x : w)
+            if (!(x > 0.0f && x <= 3.402823466e38f)) return CLEORA_E_INPUT;
+    }
+    return CLEORA_OK;
+}
+
+void embed_batch_impl(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graphs,
+                      uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
+                      void *stream);
+
+}  // namespace
+
+extern "C" {
+
 int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graphs,
                        uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
                        void *stream)
@@ -1075,8 +1113,53 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
     cleora::TraceRange trace_range("cleora_embed_batch");
     if (!c || !graphs || !out) return fail(CLEORA_E_INVAL, "NULL argument");
     if (n_graphs < 1) return fail(CLEORA_E_INVAL, "n_graphs must be >= 1");
-    if (k < 0) return fail(CLEORA_E_INVAL, "k must be >= 0");
-    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
+    c->batch_status.assign((size_t)n_graphs, CLEORA_OK);
+    auto all = [&](int32_t code) {
+        std::fill(c->batch_status.begin(), c->batch_status.end(), code);
+    };
+    try {
+        embed_batch_impl(c, n_graphs, graphs, flags, dim, dtype, k, out, stream);
+    } catch (const Error &e) {
+        if (e.code != CLEORA_E_INPUT) {
+            all(e.code);
+        } else {
+            DeviceGuard dg(c->device);
+            for (int32_t g = 0; g < n_graphs; ++g) c->batch_status[g] = graph_status(graphs[g]);
+        }
+        throw;
+    } catch (const std::bad_alloc &) {
+        all(CLEORA_E_NOMEM);
+        throw;
+    } catch (...) {
+        all(CLEORA_E_DEVICE);
+        throw;
+    }
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_batch_status(cleora_ctx *c, int32_t n_graphs, int32_t *status)
+{
+    ABI_BEGIN
+    if (!c || !status) return fail(CLEORA_E_INVAL, "NULL argument");
+    if (c->batch_status.empty()) return fail(CLEORA_E_STATE, "no cleora_embed_batch call yet");
+    if (n_graphs != (int32_t)c->batch_status.size())
+        return fail(CLEORA_E_INVAL, "n_graphs differs from the last batch");
+    std::copy(c->batch_status.begin(), c->batch_status.end(), status);
+    return CLEORA_OK;
+    ABI_END
+}
+
+}  // extern "C"
+
+namespace {
+
+void embed_batch_impl(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graphs,
+                      uint32_t flags, int32_t dim, int32_t dtype, int32_t k, void *const *out,
+                      void *stream)
+{
+    if (k < 0) throw Error(CLEORA_E_INVAL, "k must be >= 0");
+    if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) throw Error(CLEORA_E_INVAL, "unknown flag");
     check_dim(dim, dtype);
     std::vector<int64_t> row0((size_t)n_graphs + 1, 0), eoff((size_t)n_graphs + 1, 0);
     std::vector<uint64_t> seeds((size_t)n_graphs);
@@ -1084,8 +1167,8 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
     for (int32_t g = 0; g < n_graphs; ++g) {
         const cleora_graph &G = graphs[g];
         check_graph_sizes(G.n_nodes, G.n_edges);
-        if (G.n_edges > 0 && (!G.src || !G.dst)) return fail(CLEORA_E_INVAL, "graph src/dst NULL");
-        if (!out[g]) return fail(CLEORA_E_INVAL, "output pointer NULL");
+        if (G.n_edges > 0 && (!G.src || !G.dst)) throw Error(CLEORA_E_INVAL, "graph src/dst NULL");
+        if (!out[g]) throw Error(CLEORA_E_INVAL, "output pointer NULL");
         row0[g + 1] = row0[g] + G.n_nodes;
         eoff[g + 1] = eoff[g] + G.n_edges;
         seeds[g] = G.seed;
@@ -1132,9 +1215,11 @@ int cleora_embed_batch(cleora_ctx *c, int32_t n_graphs, const cleora_graph *grap
     }
     // the host vectors above must outlive the copies that read them
     CLEORA_HIP(hipStreamSynchronize(s));
-    return CLEORA_OK;
-    ABI_END
 }
+
+}  // namespace
+
+extern "C" {
 
 int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream)
 {

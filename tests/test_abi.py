@@ -90,6 +90,7 @@ def test_more_error_paths_without_gpu(lib):
     assert lib.cleora_embed_blocked(null, 16, 4, 0, 1, 2, null, 16, null) == _lib.E_INVAL
     assert lib.cleora_release_scratch(null) == _lib.E_INVAL
     assert lib.cleora_set_slices(null, 64) == _lib.E_INVAL
+    assert lib.cleora_batch_status(null, 1, null) == _lib.E_INVAL
     # server: null out, and bad parameters, rejected before any context is made
     assert lib.cleora_server_create(null, 0, 16, 0, 2, 2, 1 << 20, 1, 1, 0) == _lib.E_INVAL
     h = ctypes.c_void_p()

@@ -509,3 +509,29 @@ def test_batch_directed_weighted_equals_solo(cl, empty_keep):
         assert np.array_equal(o, solo), g.name
         want = oracle_embed(g, 40, 3, s, empty_keep=empty_keep)
         assert np.abs(o - want).max() <= F32_TOL
+
+
+def test_batch_status_names_the_bad_graphs(cl):
+    # one graph with an id out of range, one with a negative weight: the
+    # call fails with E_INPUT, the status names them, the rest go again
+    from paper_2102_02302_amd import _lib
+    gs = [gen.erdos_renyi(300, 900, 70 + i) for i in range(4)]
+    bad_id = gen.Graph(gs[1].n, gs[1].src.copy(), gs[1].dst.copy(), None, False, "bad id")
+    bad_id.dst[7] = gs[1].n
+    w = np.ones(gs[3].m, np.float32)
+    w[5] = -1.0
+    bad_w = gen.Graph(gs[3].n, gs[3].src, gs[3].dst, w, False, "bad weight")
+    batch = [gs[0], bad_id, gs[2], bad_w]
+    with cl.Context(0) as ctx:
+        with pytest.raises(cl.CleoraError):
+            cl.batch_status(ctx, 4)  # no batch call yet
+        with pytest.raises(cl.CleoraError) as e:
+            cl.embed_batch(ctx, batch, 32, 2, [1, 2, 3, 4])
+        assert e.value.code == _lib.E_INPUT
+        assert cl.batch_status(ctx, 4) == [_lib.OK, _lib.E_INPUT, _lib.OK, _lib.E_INPUT]
+        with pytest.raises(cl.CleoraError):
+            cl.batch_status(ctx, 3)  # not the last call's count
+        outs = cl.embed_batch(ctx, [gs[0], gs[2]], 32, 2, [1, 3])
+        assert cl.batch_status(ctx, 2) == [_lib.OK, _lib.OK]
+    for g, sd, out in ((gs[0], 1, outs[0]), (gs[2], 3, outs[1])):
+        assert np.array_equal(out.cpu().numpy(), gpu_embed(cl, g, 32, 2, sd))
