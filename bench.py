@@ -213,10 +213,35 @@ def served_main(args) -> dict:
         return servers[max_group]
 
     try:
-        return _served_runs(args, jobs, nnz_of, graphs, dim, k, server)
+        out = _served_runs(args, jobs, nnz_of, graphs, dim, k, server)
     finally:
         for srv in servers.values():
             srv.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _served_cpu_baseline(trace, graphs, dim, k)
+    return out
+
+
+def _served_cpu_baseline(trace, graphs, dim: int, k: int, n_sample: int = 200) -> dict:
+    """The FP64 oracle on the host cores over a seeded random sample of the
+    stream's requests, one after another, whole path each (adjacency, M,
+    T_0, k iterations)."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(2102)
+    idx = rng.choice(len(graphs), size=min(n_sample, len(graphs)), replace=False)
+    t0 = time.perf_counter()
+    edge_dims = 0
+    for i in idx:
+        g = graphs[i]
+        oracle.embed(g, dim, k, trace[i].seed)
+        edge_dims += k * (g.m if g.directed else 2 * g.m) * dim
+    dt = time.perf_counter() - t0
+    return {"value": round(len(idx) / dt, 2), "unit": "req/s", "cores": oracle.get_threads(),
+            "kind": "oracle", "gedge_dims_per_s": round(edge_dims / dt / 1e9, 4),
+            "sample": f"{len(idx)} random requests of the stream (seed 2102), whole path each, "
+                      f"FP64, {dt:.1f}s (edge-dims counted before repeated pairs merge)"}
 
 
 def _served_runs(args, jobs, nnz_of, graphs, dim, k, server) -> dict:
@@ -499,6 +524,7 @@ def main():
                           "value": b["p50_ms"], "unit": "ms", "higher_is_better": False,
                           "p99_ms": b["p99_ms"], "n_gpus": 1, "dtype": args.served_dtype,
                           "data": "synthetic", "config": {"workload": "served Chung-Lu stream"},
+                          "cpu_baseline": res.pop("cpu_baseline", None),
                           "served": res}), flush=True)
         return
 

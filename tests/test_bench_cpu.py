@@ -124,3 +124,11 @@ def test_every_trace_summary_is_of_the_current_source():
         text = open(os.path.join(prof, name)).read()
         if name.endswith("_trace.txt") or name.endswith(".json"):
             assert h in text, name
+
+
+def test_served_cpu_baseline_on_a_small_stream():
+    trace = gen.served_trace(6, 1.0, seed=3, n_hi=400)
+    graphs = gen.materialize(trace)
+    r = bench._served_cpu_baseline(trace, graphs, 16, 2, n_sample=4)
+    assert r["kind"] == "oracle" and r["unit"] == "req/s" and r["value"] > 0
+    assert r["cores"] >= 1 and r["sample"].startswith("4 random requests")
