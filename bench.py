@@ -416,9 +416,16 @@ def batched_main(args) -> dict:
         print(f"[batched] {name}: {res[name]}", flush=True)
     ctx.close()
     base = res["one_at_a_time_f32"]["ms"]
-    return {"graphs": len(graphs), "nodes": sum(g.n for g in graphs), "nnz": nnz, "dim": dim,
-            "k": k, "results": res,
-            "speedup_vs_one_at_a_time_f32": {n: round(base / r["ms"], 2) for n, r in res.items()}}
+    out = {"graphs": len(graphs), "nodes": sum(g.n for g in graphs), "nnz": nnz, "dim": dim,
+           "k": k, "results": res,
+           "speedup_vs_one_at_a_time_f32": {n: round(base / r["ms"], 2) for n, r in res.items()}}
+    if not args.no_cpu_baseline:
+        # the oracle over a seeded sample of the batch's graphs, in graphs/s
+        cb = _served_cpu_baseline(trace, graphs, dim, k, n_sample=100)
+        cb["unit"] = "graphs/s"
+        cb["sample"] = cb["sample"].replace("requests of the stream", "graphs of the batch")
+        out["cpu_baseline"] = cb
+    return out
 
 
 def parse():
@@ -503,6 +510,7 @@ def main():
                           "dtype": "bf16", "data": "synthetic",
                           "config": {"workload": "batch of Chung-Lu graphs",
                                      "graphs": res["graphs"]},
+                          "cpu_baseline": res.pop("cpu_baseline", None),
                           "batched": res}), flush=True)
         return
     if args.blocked:
