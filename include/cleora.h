@@ -131,8 +131,9 @@ int cleora_propagate(cleora_ctx *ctx, int32_t k, void *stream);
  *   out     N x dim (dtype), row stride ld_out >= dim elements; device or
  *           host memory (pinned for speed); written block by block
  * Results: T_0 entries are the same as cleora_init's (keyed by the full
- * width); every iteration equals the unblocked one except for the order in
- * which a row's squared norm is summed (block by block, FP32), and with a
+ * width); every iteration differs from the unblocked one in float32
+ * rounding only (a narrower block may gather several entries at once in
+ * lane groups, and each squared norm is summed block by block), and with a
  * single block the result is bit-identical to init + propagate.  Rows
  * follow the graph's CLEORA_EMPTY_KEEP flag.  The context keeps its graph
  * and holds no embedding afterwards (E_STATE for cleora_propagate until

@@ -168,8 +168,8 @@ class Context:
                       stream=None):
         """T_k of the context's graph computed ``block`` columns at a time
         (for embeddings too wide for two N x dim device buffers): the result
-        of init(dim, dtype, seed) + propagate(k) up to the order of each
-        row's squared-norm sum.  ``out`` is an N x dim tensor of the dtype
+        of init(dim, dtype, seed) + propagate(k) up to float32 summation
+        order.  ``out`` is an N x dim tensor of the dtype
         (device, or pinned host memory for graphs larger than the device);
         a device tensor is allocated when it is None.  The context keeps its
         graph and holds no embedding afterwards."""
@@ -353,7 +353,7 @@ def embed_blocked(g, dim: int, block: int, k: int, seed: int = 0, dtype="f32",
                   device: int = 0, empty_keep: bool = False, out=None):
     """Whole path for one graph with the embedding computed ``block`` columns
     at a time (``Context.embed_blocked``); same result as ``embed`` up to
-    the order of each row's squared-norm sum."""
+    float32 summation order."""
     with Context(device) as ctx:
         ctx.build_graph(g, empty_keep=empty_keep)
         return ctx.embed_blocked(dim, block, k, dtype, seed, out=out)

@@ -6,7 +6,7 @@ Bars: T_0 bit-exact for any block width (entries keyed by the full width);
 float32 within max-abs 1e-5 of the oracle; bfloat16 storage within max-abs
 4e-3 and minimum row cosine 0.9999; one block bit-identical to init +
 propagate (the same arithmetic step for step); several blocks within 2e-6 of
-the unblocked path (only the order of each row's squared-norm sum differs).
+the unblocked path (float32 summation order only).
 """
 
 import ctypes
