@@ -156,3 +156,14 @@ def test_embed_with_slices(cl):
     g = graphs()[0]
     got = cl.embed(g, 256, 3, 4, slices=64).cpu().numpy()
     assert np.array_equal(got, run(cl, g, 256, 3, 4, 64))
+
+
+def test_release_scratch_keeps_a_sliced_embedding(cl):
+    g = graphs()[1]
+    want = run(cl, g, 256, 3, 6, 64)
+    with cl.Context(0) as ctx:
+        ctx.set_slices(64)
+        ctx.build_graph(g).init(256, "f32", 6).propagate(2)
+        ctx.release_scratch()  # the slice buffers belong to the embedding
+        ctx.propagate(1)
+        assert np.array_equal(ctx.embedding().cpu().numpy(), want)
