@@ -92,20 +92,22 @@ def rowwise_report(got, want):
 
 
 @pytest.mark.timeout(900)
-def test_chunglu1m_full_parity(cl):
-    g, dim, k, dtype = gen.workload("chunglu1m")
-    with cl.Context(0) as ctx:
-        ctx.build_graph(g).init(dim, dtype, 2102).propagate(k)
-        got = ctx.embedding().cpu().numpy()
-        ctx.init(dim, "bf16", 2102).propagate(k)
-        got16 = ctx.embedding("f32").cpu().numpy().astype(np.float64)
-    want = oracle.embed(g, dim, k, 2102)
-    err = np.abs(got.astype(np.float64) - want).max()
-    err16, cos16 = rowwise_report(got16, want)
-    print(f"chunglu1m k={k} vs FP64 oracle, every value: FP32 max-abs {err:.3e}; "
-          f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}")
-    assert err <= F32_TOL
-    assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
+def test_chunglu1m_full_parity(cl, capsys):
+    # minutes of host work: let its progress lines through the capture
+    with capsys.disabled():
+        g, dim, k, dtype = gen.workload("chunglu1m")
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g).init(dim, dtype, 2102).propagate(k)
+            got = ctx.embedding().cpu().numpy()
+            ctx.init(dim, "bf16", 2102).propagate(k)
+            got16 = ctx.embedding("f32").cpu().numpy().astype(np.float64)
+        want = oracle.embed(g, dim, k, 2102)
+        err = np.abs(got.astype(np.float64) - want).max()
+        err16, cos16 = rowwise_report(got16, want)
+        print(f"chunglu1m k={k} vs FP64 oracle, every value: FP32 max-abs {err:.3e}; "
+              f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}")
+        assert err <= F32_TOL
+        assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
 
 
 def oracle_rows_after_k(g, dim, k, seed, rows, t0, label):
@@ -134,108 +136,115 @@ def sample_and_hubs(g, n_random, n_top, seed):
 
 
 @pytest.mark.timeout(900)
-def test_bipartite6m_vs_oracle(cl):
+def test_bipartite6m_vs_oracle(cl, capsys):
     """Weighted bipartite graph (repeated events summed, FP64 row sums):
     FP32 and BF16 after all k iterations against the full FP64 oracle on
     100k random rows and the 1000 highest-degree rows; unit rows and zero
     rows everywhere; BF16 against FP32 on every row."""
-    import torch
-    t0 = time.time()
-    g, dim, k, _ = gen.workload("bipartite6m")
-    rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 1)
-    idx = torch.as_tensor(rows, device="cuda")
-    with cl.Context(0) as ctx:
-        ctx.build_graph(g).init(dim, "f32", 7).propagate(k)
-        f32_k = ctx.embedding()
-        got32 = f32_k[idx].cpu().numpy().astype(np.float64)
-        check_properties(f32_k, deg, 1e-5)
-        ctx.init(dim, "bf16", 7).propagate(k)
-        bf_k = ctx.embedding("f32")
-        got16 = bf_k[idx].cpu().numpy().astype(np.float64)
-        check_properties(bf_k, deg, 1e-2)
-        d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
-        del f32_k, bf_k
-        torch.cuda.empty_cache()
-    print(f"bipartite6m GPU done ({time.time() - t0:.0f}s)", flush=True)
-    want = oracle_rows_after_k(g, dim, k, 7, rows, t0, "bipartite6m")
-    for name, m in (("random 100k", np.isin(rows, sample)), ("top-1000 degree", np.isin(rows, top))):
-        e32 = float(np.abs(got32[m] - want[m]).max())
-        e16, c16 = rowwise_report(got16[m], want[m])
-        print(f"bipartite6m k={k} vs FP64 oracle, {name} rows: FP32 max-abs {e32:.3e}; "
-              f"BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
-        assert e32 <= F32_TOL
-        assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
-    print(f"bipartite6m k={k} BF16 vs FP32 (GPU, all rows): max-abs {d_all:.3e} "
-          f"min-cos {cos_all:.7f}")
-    assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS
+    # minutes of host work: let its progress lines through the capture
+    with capsys.disabled():
+        import torch
+        t0 = time.time()
+        g, dim, k, _ = gen.workload("bipartite6m")
+        rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 1)
+        idx = torch.as_tensor(rows, device="cuda")
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g).init(dim, "f32", 7).propagate(k)
+            f32_k = ctx.embedding()
+            got32 = f32_k[idx].cpu().numpy().astype(np.float64)
+            check_properties(f32_k, deg, 1e-5)
+            ctx.init(dim, "bf16", 7).propagate(k)
+            bf_k = ctx.embedding("f32")
+            got16 = bf_k[idx].cpu().numpy().astype(np.float64)
+            check_properties(bf_k, deg, 1e-2)
+            d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
+            del f32_k, bf_k
+            torch.cuda.empty_cache()
+        print(f"bipartite6m GPU done ({time.time() - t0:.0f}s)", flush=True)
+        want = oracle_rows_after_k(g, dim, k, 7, rows, t0, "bipartite6m")
+        strata = (("random 100k", np.isin(rows, sample)), ("top-1000 degree", np.isin(rows, top)))
+        for name, m in strata:
+            e32 = float(np.abs(got32[m] - want[m]).max())
+            e16, c16 = rowwise_report(got16[m], want[m])
+            print(f"bipartite6m k={k} vs FP64 oracle, {name} rows: FP32 max-abs {e32:.3e}; "
+                  f"BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
+            assert e32 <= F32_TOL
+            assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
+        print(f"bipartite6m k={k} BF16 vs FP32 (GPU, all rows): max-abs {d_all:.3e} "
+              f"min-cos {cos_all:.7f}")
+        assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS
 
 
 @pytest.mark.timeout(1200)
-def test_chunglu10m_sampled(cl):
-    import torch
-    gen.graphs.PROGRESS = True  # a few minutes of drawing: say so as it goes
-    try:
-        g, dim, k, _ = gen.workload("chunglu10m")
-    finally:
-        gen.graphs.PROGRESS = False
-    rows, deg = sample_rows(g, 1000, 2)
-    want1 = oracle.t1_rows(g, rows, dim, 9)
-    idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
-    with cl.Context(0) as ctx:
-        ctx.build_graph(g).init(dim, "f32", 9).propagate(1)
-        f32_1 = ctx.embedding()[idx].cpu().numpy().astype(np.float64)
-        torch.cuda.empty_cache()
-        ctx.propagate(k - 1)
-        f32_k = ctx.embedding()
-        check_properties(f32_k, deg, 1e-5)
-        ctx.init(dim, "bf16", 9).propagate(1)
-        bf_1 = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
-        torch.cuda.empty_cache()
-        ctx.propagate(k - 1)
-        bf_k = ctx.embedding("f32")
-        check_properties(bf_k, deg, 1e-2)
-        d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
-        del f32_k, bf_k
-    err32 = np.abs(f32_1 - want1).max()
-    err16, cos16 = rowwise_report(bf_1, want1)
-    print(f"chunglu10m k=1 sampled {rows.size} rows: FP32 max-abs {err32:.3e}; "
-          f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}; k={k} BF16 vs FP32 (GPU, all rows): "
-          f"max-abs {d_all:.3e} min-cos {cos_all:.7f}")
-    assert err32 <= F32_TOL
-    assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
-    assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS
+def test_chunglu10m_sampled(cl, capsys):
+    # minutes of host work: let its progress lines through the capture
+    with capsys.disabled():
+        import torch
+        gen.graphs.PROGRESS = True  # a few minutes of drawing: say so as it goes
+        try:
+            g, dim, k, _ = gen.workload("chunglu10m")
+        finally:
+            gen.graphs.PROGRESS = False
+        rows, deg = sample_rows(g, 1000, 2)
+        want1 = oracle.t1_rows(g, rows, dim, 9)
+        idx = torch.as_tensor(rows.astype(np.int64), device="cuda")
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g).init(dim, "f32", 9).propagate(1)
+            f32_1 = ctx.embedding()[idx].cpu().numpy().astype(np.float64)
+            torch.cuda.empty_cache()
+            ctx.propagate(k - 1)
+            f32_k = ctx.embedding()
+            check_properties(f32_k, deg, 1e-5)
+            ctx.init(dim, "bf16", 9).propagate(1)
+            bf_1 = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
+            torch.cuda.empty_cache()
+            ctx.propagate(k - 1)
+            bf_k = ctx.embedding("f32")
+            check_properties(bf_k, deg, 1e-2)
+            d_all, cos_all = compare_gpu(bf_k, f32_k, deg)
+            del f32_k, bf_k
+        err32 = np.abs(f32_1 - want1).max()
+        err16, cos16 = rowwise_report(bf_1, want1)
+        print(f"chunglu10m k=1 sampled {rows.size} rows: FP32 max-abs {err32:.3e}; "
+              f"BF16 max-abs {err16:.3e} min-cos {cos16:.7f}; k={k} BF16 vs FP32 (GPU, all rows): "
+              f"max-abs {d_all:.3e} min-cos {cos_all:.7f}")
+        assert err32 <= F32_TOL
+        assert err16 <= BF16_MAXABS and cos16 >= BF16_MINCOS
+        assert d_all <= 2 * BF16_MAXABS and cos_all >= BF16_MINCOS
 
 
 @pytest.mark.timeout(2400)
 @pytest.mark.skipif(os.environ.get("CLEORA_FULL_ORACLE") != "1",
                     reason="opt-in (CLEORA_FULL_ORACLE=1): the FP64 oracle at N = 10M, "
                            "d = 1024 needs about 180 GB of host memory")
-def test_chunglu10m_all_iterations_vs_oracle(cl):
-    import torch
-    t0 = time.time()
-    gen.graphs.PROGRESS = True
-    try:
-        g, dim, k, _ = gen.workload("chunglu10m")
-    finally:
-        gen.graphs.PROGRESS = False
-    rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 3)
-    idx = torch.as_tensor(rows, device="cuda")
-    got = {}
-    with cl.Context(0) as ctx:
-        for dt in ("f32", "bf16"):
-            ctx.build_graph(g).init(dim, dt, 11).propagate(k)
-            got[dt] = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
-            torch.cuda.empty_cache()
-    print(f"GPU FP32 and BF16 done ({time.time() - t0:.0f}s)", flush=True)
+def test_chunglu10m_all_iterations_vs_oracle(cl, capsys):
+    # minutes of host work: let its progress lines through the capture
+    with capsys.disabled():
+        import torch
+        t0 = time.time()
+        gen.graphs.PROGRESS = True
+        try:
+            g, dim, k, _ = gen.workload("chunglu10m")
+        finally:
+            gen.graphs.PROGRESS = False
+        rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 3)
+        idx = torch.as_tensor(rows, device="cuda")
+        got = {}
+        with cl.Context(0) as ctx:
+            for dt in ("f32", "bf16"):
+                ctx.build_graph(g).init(dim, dt, 11).propagate(k)
+                got[dt] = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
+                torch.cuda.empty_cache()
+        print(f"GPU FP32 and BF16 done ({time.time() - t0:.0f}s)", flush=True)
 
-    want = oracle_rows_after_k(g, dim, k, 11, rows, t0, "chunglu10m")
+        want = oracle_rows_after_k(g, dim, k, 11, rows, t0, "chunglu10m")
 
-    in_sample = np.isin(rows, sample)
-    in_top = np.isin(rows, top)
-    for name, m in (("random 100k", in_sample), ("top-1000 degree", in_top)):
-        e32 = float(np.abs(got["f32"][m] - want[m]).max())
-        e16, c16 = rowwise_report(got["bf16"][m], want[m])
-        print(f"chunglu10m k={k} vs FP64 oracle, {name} rows: FP32 max-abs {e32:.3e}; "
-              f"BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
-        assert e32 <= F32_TOL
-        assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
+        in_sample = np.isin(rows, sample)
+        in_top = np.isin(rows, top)
+        for name, m in (("random 100k", in_sample), ("top-1000 degree", in_top)):
+            e32 = float(np.abs(got["f32"][m] - want[m]).max())
+            e16, c16 = rowwise_report(got["bf16"][m], want[m])
+            print(f"chunglu10m k={k} vs FP64 oracle, {name} rows: FP32 max-abs {e32:.3e}; "
+                  f"BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
+            assert e32 <= F32_TOL
+            assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
