@@ -24,7 +24,9 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 from typing import Callable, Optional
 
 import numpy as np
@@ -33,6 +35,28 @@ import numpy as np
 PROGRESS = False
 
 BASE_SEED = 2102
+
+# threads for the inverse-CDF lookups of large draws (the machine's CPU share)
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _inverse_cdf(cdf: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Index of the first CDF entry above each uniform draw, capped at the
+    last index.  Large draws are looked up in parallel slices (numpy
+    releases the GIL here); the result does not depend on the slicing."""
+    n = cdf.size
+    if u.size < (1 << 22) or THREADS < 2:
+        return np.minimum(np.searchsorted(cdf, u, side="right"), n - 1)
+    out = np.empty(u.size, np.int64)
+    bounds = np.linspace(0, u.size, 4 * THREADS + 1).astype(np.int64)
+
+    def look(i):
+        a, b = bounds[i], bounds[i + 1]
+        out[a:b] = np.minimum(np.searchsorted(cdf, u[a:b], side="right"), n - 1)
+
+    with ThreadPoolExecutor(THREADS) as ex:
+        list(ex.map(look, range(bounds.size - 1)))
+    return out
 
 
 @dataclasses.dataclass
@@ -131,7 +155,7 @@ def chung_lu(n: int, m: int, exponent: float, seed: int) -> Graph:
     cdf = _power_law_cdf(n, exponent)
 
     def sampler(k: int) -> np.ndarray:
-        return np.minimum(np.searchsorted(cdf, rng.random(k), side="right"), n - 1)
+        return _inverse_cdf(cdf, rng.random(k))
 
     lo, hi = _distinct_pairs(rng, n, m, sampler)
     src, dst = _relabel(rng, n, lo, hi)
@@ -149,7 +173,7 @@ def bipartite_zipf(n_users: int, n_items: int, n_events: int, zipf_a: float,
     rank_w = np.arange(1, n_items + 1, dtype=np.float64) ** (-zipf_a)
     cdf = np.cumsum(rank_w)
     cdf /= cdf[-1]
-    ranks = np.minimum(np.searchsorted(cdf, rng.random(n_events), side="right"), n_items - 1)
+    ranks = _inverse_cdf(cdf, rng.random(n_events))
     item_of_rank = rng.permutation(n_items)
     items = n_users + item_of_rank[ranks]
     w = rng.lognormal(0.0, 1.0, n_events).astype(np.float32)
