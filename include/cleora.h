@@ -272,12 +272,26 @@ int cleora_autotune(cleora_ctx *ctx, int32_t *pack, int32_t *persistent, float *
                     void *stream);
 
 /* Kernel timing for measurement: when on, the library records HIP events
- * around every SpMM+normalise launch on the launch stream and accumulates
- * their durations; cleora_kernel_time returns the total milliseconds and
- * the number of launches timed since the last reset (and resets). */
+ * around every SpMM+normalise (and combine) launch on the launch stream --
+ * inside the captured graph when k >= 2 iterations run as one, so timed
+ * runs take the same launch path as untimed ones -- and accumulates their
+ * durations; cleora_kernel_time returns the total milliseconds and the
+ * number of launches timed since the last reset (and resets).  A graph's
+ * events are read before its next replay (which then waits for the
+ * previous one) or by cleora_kernel_time (which waits for the device
+ * work). */
 int cleora_set_timing(cleora_ctx *ctx, int on);
 int cleora_kernel_time(cleora_ctx *ctx, double *spmm_ms, int64_t *spmm_launches,
                        double *combine_ms, int64_t *combine_launches);
+
+/* Launch statistics since the context was created: captured k-iteration
+ * graphs instantiated, and graph replays.  k >= 2 iterations run as one
+ * captured graph, kept per (k, starting buffer, timing) together with the
+ * launch parameters it was captured with; a later call replays it whenever
+ * those are unchanged (e.g. a graph of the same shape rebuilt into the
+ * same buffers) and captures anew otherwise.  Any pointer may be NULL.
+ * Errors: E_INVAL (NULL ctx). */
+int cleora_launch_stats(cleora_ctx *ctx, int64_t *graph_instantiations, int64_t *graph_launches);
 
 /* ------------------------------------------------ hypergraph expansion */
 

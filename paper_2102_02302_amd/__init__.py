@@ -334,6 +334,13 @@ class Context:
         return {"spmm_ms": a.value, "spmm_launches": na.value, "combine_ms": b.value,
                 "combine_launches": nb.value}
 
+    def launch_stats(self) -> dict:
+        """Captured k-iteration graphs instantiated, and their replays, since
+        the context was created."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(self._lib.cleora_launch_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return {"graph_instantiations": a.value, "graph_launches": b.value}
+
 
 def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
           empty_keep: bool = False, chunk: int = 0, slices: int = 0):

@@ -3,6 +3,7 @@
 
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -132,6 +133,22 @@ void launch_scale_rows(float *E, int64_t n, int32_t ld, const float *inv, hipStr
 
 // ------------------------------------------------------------------- ctx
 
+namespace cleora {
+// A captured k-iteration loop and the launch parameters it was captured
+// with: it is replayed only while they are unchanged, so rebuilding a graph
+// of the same shape into the same buffers reuses it.
+struct LoopGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> sig;
+    hipEvent_t done = nullptr;  // recorded after every replay
+    bool launched = false;
+    // timing events recorded by the graph around each launch (captured
+    // with timing on); `unread`: replayed since they were last read
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmm, ev_comb;
+    bool unread = false;
+};
+}  // namespace cleora
+
 struct cleora_ctx {
     int device = 0;
 
@@ -171,18 +188,22 @@ struct cleora_ctx {
     // per-graph status of the last cleora_embed_batch call
     std::vector<int32_t> batch_status;
 
-    // captured k-iteration graphs, keyed by (k, starting parity)
-    std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
+    // captured k-iteration graphs, keyed by (k, starting parity, timing)
+    std::map<std::tuple<int32_t, int, bool>, cleora::LoopGraph> graphs;
+    int64_t graph_instantiations = 0, graph_launches = 0;
     hipStream_t cap_stream = nullptr;
     // side stream of cleora_build_init (T_0 written during the build)
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-    // timing
+    // timing: events of eager launches (from a reused pool) and the totals
+    // read so far from those and from captured graphs' events
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmm, ev_comb;
     size_t ev_next = 0;
+    double t_spmm_ms = 0, t_comb_ms = 0;
+    int64_t t_spmm_n = 0, t_comb_n = 0;
 };
 
 namespace cleora {

@@ -146,32 +146,45 @@ hipEvent_t take_event(cleora_ctx *c)
     return e;
 }
 
-// One spmm (+ combine) launch of enqueue_steps, with timing events when on.
+// Where the timing events of queued launches go: the context's eager list
+// (events from its pool) or a graph being captured (fresh events that the
+// graph owns).  No lists: no timing.
+struct Timers {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *spmm = nullptr, *comb = nullptr;
+    bool fresh = false;
+};
+
+hipEvent_t timer_event(cleora_ctx *c, const Timers &t)
+{
+    if (!t.fresh) return take_event(c);
+    hipEvent_t e;
+    CLEORA_HIP(hipEventCreate(&e));
+    return e;
+}
+
+// One spmm (+ combine) launch of enqueue_steps, with timing events when
+// asked for.
 void launch_step(cleora_ctx *c, const cleora::Variant &v, const StepDesc &d,
-                 const StepDesc *dev_desc, hipStream_t s)
+                 const StepDesc *dev_desc, hipStream_t s, const Timers &t)
 {
     hipEvent_t a = nullptr, b = nullptr;
-    if (c->timing) {
-        a = take_event(c);
-        b = take_event(c);
+    if (t.spmm) {
+        a = timer_event(c, t);
+        b = timer_event(c, t);
+        t.spmm->emplace_back(a, b);
         CLEORA_HIP(hipEventRecord(a, s));
     }
     cleora::launch_spmm(v, d, s);
-    if (c->timing) {
-        CLEORA_HIP(hipEventRecord(b, s));
-        c->ev_spmm.emplace_back(a, b);
-    }
+    if (t.spmm) CLEORA_HIP(hipEventRecord(b, s));
     if (c->n_long > 0) {
-        if (c->timing) {
-            a = take_event(c);
-            b = take_event(c);
+        if (t.comb) {
+            a = timer_event(c, t);
+            b = timer_event(c, t);
+            t.comb->emplace_back(a, b);
             CLEORA_HIP(hipEventRecord(a, s));
         }
         cleora::launch_combine(v, dev_desc, 1, c->n_long, s);
-        if (c->timing) {
-            CLEORA_HIP(hipEventRecord(b, s));
-            c->ev_comb.emplace_back(a, b);
-        }
+        if (t.comb) CLEORA_HIP(hipEventRecord(b, s));
     }
 }
 
@@ -181,7 +194,7 @@ void launch_step(cleora_ctx *c, const cleora::Variant &v, const StepDesc &d,
 // (Applying the factors inside the next iteration's gather instead, and
 // scaling only at the end, was slower: each entry then also reads its
 // neighbour's factor from an N-long vector.)
-void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
+void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s, const Timers &tm)
 {
     const int64_t n = c->n;
     const int32_t B = c->slice_cols, S = (c->ld + B - 1) / B;
@@ -192,7 +205,7 @@ void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
             const int32_t c0 = j * B;
             const cleora::Variant v = cleora::choose_variant(CLEORA_F32, std::min(B, c->ld - c0));
             launch_step(c, v, cleora::slice_desc(c, cur, c0),
-                        c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s);
+                        c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s, tm);
         }
         cleora::launch_inv_norm(ss, inv, n, s);
         cleora::launch_scale_rows(c->E[cur ^ 1].as<float>(), n, c->ld, inv, s);
@@ -201,52 +214,143 @@ void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
 }
 
 // Queue k iterations starting from buffer parity `cur` (no state change).
-void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s)
+void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s, const Timers &tm)
 {
-    if (c->slice_cols > 0) return enqueue_sliced_steps(c, k, cur, s);
+    if (c->slice_cols > 0) return enqueue_sliced_steps(c, k, cur, s, tm);
     const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
     for (int32_t t = 0; t < k; ++t) {
-        launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
+        launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s, tm);
         cur ^= 1;
     }
 }
 
+// Add the durations of a graph's last replay to the context's totals.
+void read_graph_events(cleora_ctx *c, cleora::LoopGraph &L)
+{
+    if (!L.unread) return;
+    L.unread = false;
+    for (auto &p : L.ev_spmm) {
+        CLEORA_HIP(hipEventSynchronize(p.second));
+        float ms = 0;
+        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+        c->t_spmm_ms += ms;
+        c->t_spmm_n++;
+    }
+    for (auto &p : L.ev_comb) {
+        CLEORA_HIP(hipEventSynchronize(p.second));
+        float ms = 0;
+        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+        c->t_comb_ms += ms;
+        c->t_comb_n++;
+    }
+}
+
+// Release a captured loop after its last replay has finished.
+void free_loop(cleora::LoopGraph &L)
+{
+    if (L.done && L.launched) (void)hipEventSynchronize(L.done);
+    if (L.exec) (void)hipGraphExecDestroy(L.exec);
+    if (L.done) (void)hipEventDestroy(L.done);
+    for (auto *v : {&L.ev_spmm, &L.ev_comb})
+        for (auto &p : *v) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    L = cleora::LoopGraph{};
+}
+
 void drop_graphs(cleora_ctx *c)
 {
-    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->graphs) free_loop(kv.second);
     c->graphs.clear();
 }
 
-// k >= 2 iterations without timing run as one captured graph (cached per
-// k and starting parity): the 2k launches cost one graph launch.
+// Everything a captured k-iteration loop depends on: kernel arguments of
+// both parities (buffers, schedule sizes, layout, flags, grid choice), the
+// device descriptor tables, the slicing and timing.  Equal signatures mean
+// the captured launches are exactly the ones enqueue_steps would queue now.
+std::vector<int64_t> loop_signature(const cleora_ctx *c, int32_t k, int cur)
+{
+    std::vector<int64_t> g;
+    auto P = [&](const void *p) { g.push_back((int64_t)reinterpret_cast<uintptr_t>(p)); };
+    g.insert(g.end(), {k, cur, c->timing ? 1 : 0, c->dtype, c->ld, c->slice_cols, c->n,
+                       c->n_long});
+    P(c->desc.p);
+    P(c->slice_desc.p);
+    P(c->slice_norms.p);
+    for (int p = 0; p < 2; ++p) {
+        const StepDesc d = cleora::host_desc(c, p);
+        P(d.rp);
+        P(d.col);
+        P(d.val);
+        P(d.Ein);
+        P(d.Eout);
+        P(d.partial);
+        P(d.split_items);
+        P(d.bucket_row);
+        P(d.long_rows);
+        P(d.chunk_base);
+        g.insert(g.end(), {d.n_split, d.n_buckets, d.n_long, d.ld, d.chunk, (int64_t)d.flags,
+                           d.persist});
+    }
+    return g;
+}
+
+// The captured loop of k iterations from the current parity, captured (and
+// instantiated) only when no loop with the current launch parameters
+// exists.
+cleora::LoopGraph &loop_graph(cleora_ctx *c, int32_t k)
+{
+    cleora::LoopGraph &L = c->graphs[std::make_tuple(k, c->cur, c->timing)];
+    std::vector<int64_t> sig = loop_signature(c, k, c->cur);
+    if (L.exec && L.sig == sig) return L;
+    free_loop(L);
+    if (!c->cap_stream) CLEORA_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    Timers tm;
+    if (c->timing) tm = Timers{&L.ev_spmm, &L.ev_comb, true};
+    try {
+        CLEORA_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+        CLEORA_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue_steps(c, k, c->cur, c->cap_stream, tm);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        CLEORA_HIP(hipStreamEndCapture(c->cap_stream, &g));
+        const hipError_t e = hipGraphInstantiate(&L.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        CLEORA_HIP(e);
+    } catch (...) {
+        free_loop(L);
+        throw;
+    }
+    L.sig = std::move(sig);
+    c->graph_instantiations++;
+    return L;
+}
+
+// k >= 2 iterations run as one captured graph (cached per k, starting
+// parity and timing): the 2k launches cost one graph launch.  With timing
+// on, the graph records events around its launches; they are read before
+// the next replay overwrites them, or by cleora_kernel_time.
 void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
 {
     if (k <= 0) return;
-    if (k >= 2 && !c->timing) {
-        const auto key = std::make_pair(k, c->cur);
-        auto it = c->graphs.find(key);
-        if (it == c->graphs.end()) {
-            if (!c->cap_stream)
-                CLEORA_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-            hipGraph_t g = nullptr;
-            CLEORA_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-            try {
-                enqueue_steps(c, k, c->cur, c->cap_stream);
-            } catch (...) {
-                (void)hipStreamEndCapture(c->cap_stream, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            CLEORA_HIP(hipStreamEndCapture(c->cap_stream, &g));
-            hipGraphExec_t ex = nullptr;
-            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            CLEORA_HIP(e);
-            it = c->graphs.emplace(key, ex).first;
-        }
-        CLEORA_HIP(hipGraphLaunch(it->second, s));
+    if (k >= 2) {
+        cleora::LoopGraph &L = loop_graph(c, k);
+        read_graph_events(c, L);
+        CLEORA_HIP(hipGraphLaunch(L.exec, s));
+        CLEORA_HIP(hipEventRecord(L.done, s));
+        L.launched = true;
+        L.unread = c->timing;
+        c->graph_launches++;
     } else {
-        enqueue_steps(c, k, c->cur, s);
+        Timers tm;
+        if (c->timing) tm = Timers{&c->ev_spmm, &c->ev_comb, false};
+        enqueue_steps(c, k, c->cur, s, tm);
     }
     c->cur ^= (k & 1);
     c->iteration += k;
@@ -265,7 +369,6 @@ int device_cus(int device)
 // The two embedding buffers for n rows (the schedule comes later).
 void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
 {
-    drop_graphs(c);
     c->has_emb = false;
     c->dim = dim;
     c->dtype = dtype;
@@ -422,7 +525,6 @@ void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int6
 {
     check_graph_sizes(n_total, m_total);
     check_dim(dim, dtype);
-    drop_graphs(c);
     c->is_chunk = false;
     if (m_total > 0) {
         const unsigned blocks = (unsigned)std::min<int64_t>(ceil_div(m_total, 256), 65536);
@@ -525,7 +627,6 @@ int cleora_build_csr(cleora_ctx *c, int64_t n, int64_t m, const int32_t *src, co
     if (m > 0 && (!src || !dst)) return fail(CLEORA_E_INVAL, "src/dst is NULL");
     if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
     DeviceGuard g(c->device);
-    drop_graphs(c);
     c->is_chunk = false;
     cleora::build_graph(c, n, n, m, src, dst, w, flags, cleora::as_stream(stream));
     return CLEORA_OK;
@@ -701,7 +802,6 @@ int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t
         return fail(CLEORA_E_INVAL, "T_in must be 16-byte aligned");
     DeviceGuard g(c->device);
     hipStream_t s = cleora::as_stream(stream);
-    drop_graphs(c);
     c->is_chunk = false;
     cleora::build_graph(c, n_rows, n_cols, m, rows, cols, w, CLEORA_DIRECTED, s);
     c->dim = dim;
@@ -899,6 +999,17 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
             }
         } catch (...) {
             restore();
+            // put the default schedule back: the trial one may not match
+            // the buffers any more; without a schedule the embedding can no
+            // longer be propagated
+            try {
+                cleora::plan_schedule(c, s);
+                c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
+                                  (size_t)c->ld);
+                cleora::write_descs(c, s);
+            } catch (...) {
+                c->has_emb = false;
+            }
             throw;
         }
         restore();
@@ -906,7 +1017,6 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
         g_tune_cache[key] = best;
         append_tune_file_locked(key, best);
     }
-    drop_graphs(c);
     c->pack_req = 0;  // the cache entry now applies to this and later inits
     c->persist_req = -1;
     cleora::plan_schedule(c, s);
@@ -934,26 +1044,40 @@ int cleora_kernel_time(cleora_ctx *c, double *spmm_ms, int64_t *spmm_n, double *
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     DeviceGuard g(c->device);
-    double a = 0, b = 0;
     for (auto &p : c->ev_spmm) {
         CLEORA_HIP(hipEventSynchronize(p.second));
         float ms = 0;
         CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        a += ms;
+        c->t_spmm_ms += ms;
+        c->t_spmm_n++;
     }
     for (auto &p : c->ev_comb) {
         CLEORA_HIP(hipEventSynchronize(p.second));
         float ms = 0;
         CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        b += ms;
+        c->t_comb_ms += ms;
+        c->t_comb_n++;
     }
-    if (spmm_ms) *spmm_ms = a;
-    if (spmm_n) *spmm_n = (int64_t)c->ev_spmm.size();
-    if (comb_ms) *comb_ms = b;
-    if (comb_n) *comb_n = (int64_t)c->ev_comb.size();
     c->ev_spmm.clear();
     c->ev_comb.clear();
     c->ev_next = 0;
+    for (auto &kv : c->graphs) read_graph_events(c, kv.second);
+    if (spmm_ms) *spmm_ms = c->t_spmm_ms;
+    if (spmm_n) *spmm_n = c->t_spmm_n;
+    if (comb_ms) *comb_ms = c->t_comb_ms;
+    if (comb_n) *comb_n = c->t_comb_n;
+    c->t_spmm_ms = c->t_comb_ms = 0;
+    c->t_spmm_n = c->t_comb_n = 0;
+    return CLEORA_OK;
+    ABI_END
+}
+
+int cleora_launch_stats(cleora_ctx *c, int64_t *graph_instantiations, int64_t *graph_launches)
+{
+    ABI_BEGIN
+    if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
+    if (graph_instantiations) *graph_instantiations = c->graph_instantiations;
+    if (graph_launches) *graph_launches = c->graph_launches;
     return CLEORA_OK;
     ABI_END
 }
@@ -1013,7 +1137,6 @@ int cleora_build_chunk(cleora_ctx *c, int64_t n_global, int64_t m, const int32_t
     if (m < 1 || !src || !dst) return fail(CLEORA_E_INVAL, "a chunk needs edges");
     if (flags & ~(CLEORA_DIRECTED | CLEORA_EMPTY_KEEP)) return fail(CLEORA_E_INVAL, "unknown flag");
     DeviceGuard g(c->device);
-    drop_graphs(c);
     cleora::build_chunk(c, n_global, m, src, dst, w, flags, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
@@ -1178,7 +1301,6 @@ void embed_batch_impl(cleora_ctx *c, int32_t n_graphs, const cleora_graph *graph
     check_graph_sizes(N, M);
     DeviceGuard dg(c->device);
     hipStream_t s = cleora::as_stream(stream);
-    drop_graphs(c);
     c->is_chunk = false;
     // concatenated edge list with node offsets, then the ordinary build
     const size_t ebytes = ((size_t)std::max<int64_t>(M, 1) * (any_w ? 12 : 8) + 255) / 256 * 256;

@@ -317,6 +317,64 @@ def test_graph_replays_match_eager(cl):
         assert a.info()["iteration"] == 12
 
 
+def test_timed_graph_replays_match_untimed(cl):
+    # timing on: the captured loop records events around its launches; the
+    # bits are those of the untimed loop and of eager steps, and every
+    # launch of every replay is timed
+    g = gen.chung_lu(30_000, 200_000, 2.1, 41)
+    with cl.Context(0) as a, cl.Context(0) as b:
+        a.set_chunk(32)
+        b.set_chunk(32)
+        a.build_graph(g).init(128, "f32", 5)
+        b.build_graph(g).init(128, "f32", 5)
+        a.kernel_time()
+        a.set_timing(True)
+        for _ in range(3):
+            a.propagate(4)
+        a.set_timing(False)
+        kt = a.kernel_time()
+        assert kt["spmm_launches"] == 12 and kt["spmm_ms"] > 0
+        assert kt["combine_launches"] == 12 and kt["combine_ms"] > 0
+        for _ in range(12):
+            b.propagate(1)
+        assert np.array_equal(a.embedding().cpu().numpy(), b.embedding().cpu().numpy())
+        a.propagate(4)  # untimed loop of the same k
+        for _ in range(4):
+            b.propagate(1)
+        assert np.array_equal(a.embedding().cpu().numpy(), b.embedding().cpu().numpy())
+        assert a.kernel_time()["spmm_launches"] == 0
+
+
+def test_rebuilds_reuse_the_captured_loop(cl):
+    # the same graph rebuilt and re-initialised (as every bench step and
+    # batch does) replays the loop captured the first time; a graph of
+    # another shape is captured anew, and its results are still right
+    import torch
+    g = gen.chung_lu(20_000, 150_000, 2.1, 42)
+    h = gen.erdos_renyi(9_000, 40_000, 43)
+    dev = torch.device("cuda", 0)
+    gs, gd = torch.as_tensor(g.src).to(dev), torch.as_tensor(g.dst).to(dev)
+    hs, hd = torch.as_tensor(h.src).to(dev), torch.as_tensor(h.dst).to(dev)
+    with cl.Context(0) as ctx:
+        outs = []
+        for _ in range(4):
+            ctx.build_init(g.n, gs, gd, None, 64, "f32", seed=7)
+            ctx.propagate(4)
+            outs.append(ctx.embedding().cpu().numpy())
+        st = ctx.launch_stats()
+        assert st == {"graph_instantiations": 1, "graph_launches": 4}, st
+        assert all(np.array_equal(outs[0], o) for o in outs[1:])
+        ctx.build_init(h.n, hs, hd, None, 64, "f32", seed=7)
+        ctx.propagate(4)
+        got_h = ctx.embedding().cpu().numpy()
+        assert ctx.launch_stats()["graph_instantiations"] == 2
+        ctx.build_init(g.n, gs, gd, None, 64, "f32", seed=7)
+        ctx.propagate(4)
+        assert np.array_equal(ctx.embedding().cpu().numpy(), outs[0])
+    assert np.abs(outs[0] - oracle_embed(g, 64, 4, 7)).max() <= F32_TOL
+    assert np.abs(got_h - oracle_embed(h, 64, 4, 7)).max() <= F32_TOL
+
+
 @pytest.mark.parametrize("dim,dtype", [(32, "f32"), (128, "f32"), (256, "bf16"), (1024, "f32")])
 def test_persistent_grid_same_bits(cl, dim, dtype):
     # a persistent grid only changes which wave runs which work item
