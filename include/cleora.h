@@ -402,8 +402,14 @@ int cleora_step_multi(cleora_ctx *const *ctxs, int32_t n, void *stream);
 /* A native request server on one device: continuous batching of
  * independent graphs.  Requests are admitted in submission order, as groups
  * of up to max_group requests, when a builder thread is free, a slot (a
- * context) is free and the summed cleora_footprint_bytes of admitted
- * requests stays within budget_bytes (groups grow with the backlog).
+ * context with its staging buffer) is free and the device memory charged
+ * to the slots stays within budget_bytes (groups grow with the backlog).
+ * A request's charge is its cleora_footprint_bytes plus 12 bytes per edge
+ * (and 1 KiB) of staging.  Slots keep their buffers between groups: an
+ * idle or running slot is charged what its buffers hold, a building slot
+ * that plus its group's charge (slot buffers grow to the exact size asked
+ * for), and idle slots release their buffers, largest first, when a group
+ * needs the room.
  * Builder threads pack a group's edges into pinned staging,
  * copy them to the device once and build the group as one block-diagonal
  * graph (its CSR and T_0, each member's T_0 rows keyed by its own seed and
@@ -440,8 +446,8 @@ typedef struct {
     double done_s;      /* the result is in `out` */
 } cleora_completion;
 
-/* slots: contexts (groups in flight); budget_bytes: most summed footprint
- * of admitted requests (0: 80% of the device memory free at creation);
+/* slots: contexts (groups in flight); budget_bytes: most device memory
+ * charged to the slots (0: 80% of the device memory free at creation);
  * builders: build threads; max_group: most requests built together (1:
  * every request on its own).  flags: CLEORA_DIRECTED / CLEORA_EMPTY_KEEP
  * for every request.  Errors: E_INVAL (dim outside [1, CLEORA_MAX_DIM_*]
@@ -455,11 +461,18 @@ int cleora_server_submit(cleora_server *s, const cleora_request *req, int64_t *t
 /* Up to max completions (waiting up to wait_s seconds when none is ready). */
 int cleora_server_poll(cleora_server *s, cleora_completion *out, int32_t max, int32_t *n_out,
                        double wait_s);
-/* Steps run, request-steps run, most groups in one step, peak admitted
- * footprint, groups built, requests submitted and not yet polled.  Any
+/* Steps run, request-steps run, most groups in one step, peak charged
+ * device memory, groups built, requests submitted and not yet polled.  Any
  * output pointer may be NULL. */
 int cleora_server_stats(cleora_server *s, int64_t *steps, int64_t *stepped, int32_t *max_active,
                         int64_t *peak_bytes, int64_t *groups, int64_t *in_system);
+/* Memory accounting: the budget, the bytes charged now and at most so far
+ * (the slots' buffers plus the charges of groups being built), and the
+ * number of builds after which a slot held more than it was charged (0
+ * unless a footprint failed to bound a build).  Any output may be NULL.
+ * Errors: E_INVAL (NULL server). */
+int cleora_server_memory(cleora_server *s, int64_t *budget, int64_t *charged, int64_t *peak,
+                         int64_t *bound_exceeded);
 /* Seconds since the server was created (the clock of the completions). */
 double cleora_server_now(cleora_server *s);
 /* Stops the threads (requests not yet completed are dropped) and frees

@@ -35,7 +35,8 @@ EXPORTS = [
     "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
     "cleora_embed_batch", "cleora_batch_status", "cleora_step_multi", "cleora_server_create",
     "cleora_server_submit",
-    "cleora_server_poll", "cleora_server_stats", "cleora_server_now", "cleora_server_destroy",
+    "cleora_server_poll", "cleora_server_stats", "cleora_server_memory", "cleora_server_now",
+    "cleora_server_destroy",
     "cleora_last_error",
 ]
 
@@ -135,6 +136,8 @@ def load() -> ctypes.CDLL:
         "cleora_server_stats": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                                ctypes.POINTER(i32), ctypes.POINTER(i64),
                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "cleora_server_memory": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "cleora_server_now": (ctypes.c_double, [p]),
         "cleora_server_destroy": (None, [p]),
         "cleora_last_error": (ctypes.c_char_p, []),

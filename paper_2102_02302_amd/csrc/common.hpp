@@ -72,13 +72,14 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    bool exact = false;  // grow to the size asked for (no 1.5x step)
     // A regrowth asks for at least 1.5x the old size (the exact size if
-    // that fails), so a buffer reused for slowly growing sizes reallocates
-    // O(log) times: each free waits for the device.
+    // that fails, or with `exact`), so a buffer reused for slowly growing
+    // sizes reallocates O(log) times: each free waits for the device.
     void ensure(size_t bytes)
     {
         if (bytes <= cap && p) return;
-        const size_t grown = cap ? cap + cap / 2 : 0;
+        const size_t grown = cap && !exact ? cap + cap / 2 : 0;
         release();
         size_t b = std::max<size_t>(bytes, 256);
         hipError_t e = hipErrorMemoryAllocation;

@@ -235,6 +235,13 @@ void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int6
                           const int64_t *d_eoff, const uint64_t *d_seeds, uint32_t flags,
                           int32_t dim, int32_t dtype, hipStream_t s);
 void set_last_error(const std::string &msg);
+// Every device buffer of a context; their summed capacity; exact growth for
+// all of them (the server's memory accounting); release all but the status
+// words (the context then holds no graph and no embedding).
+std::vector<DevBuf *> ctx_buffers(cleora_ctx *c);
+int64_t ctx_device_bytes(cleora_ctx *c);
+void set_exact_growth(cleora_ctx *c);
+void release_buffers(cleora_ctx *c);
 // Column-blocked T_k (blocked.hip): dim columns, `block` at a time, into
 // out (row stride ld_out elements).  The context's graph stays; its
 // embedding buffers are reused as block buffers.

@@ -452,6 +452,40 @@ int32_t tuned_pack(const cleora_ctx *c)
     return it == g_tune_cache.end() ? 0 : it->second.pack;
 }
 
+std::vector<DevBuf *> ctx_buffers(cleora_ctx *c)
+{
+    return {&c->rp,         &c->col,        &c->val,         &c->deg,        &c->E[0],
+            &c->E[1],       &c->split_items, &c->bucket_row, &c->long_rows,  &c->chunk_base,
+            &c->partial,    &c->desc,       &c->blk_norms,   &c->chunk_ids,  &c->chunk_occ,
+            &c->t_local,    &c->t_expand,   &c->t_edges,     &c->t_wts,      &c->t_cnt,
+            &c->t_off,      &c->t_keys,     &c->t_tmp,       &c->t_head,     &c->t_pos,
+            &c->t_esum,     &c->t_lists,    &c->t_scan,      &c->t_small,    &c->multi_desc,
+            &c->slice_desc, &c->slice_norms};
+}
+
+int64_t ctx_device_bytes(cleora_ctx *c)
+{
+    int64_t b = 0;
+    for (DevBuf *d : ctx_buffers(c)) b += (int64_t)d->cap;
+    return b;
+}
+
+void set_exact_growth(cleora_ctx *c)
+{
+    for (DevBuf *d : ctx_buffers(c)) d->exact = true;
+}
+
+void release_buffers(cleora_ctx *c)
+{
+    DeviceGuard g(c->device);
+    drop_graphs(c);
+    for (DevBuf *d : ctx_buffers(c))
+        if (d != &c->t_small) d->release();  // t_small: the build's status words
+    c->has_graph = false;
+    c->has_emb = false;
+    c->is_chunk = false;
+}
+
 int32_t tuned_persist(const cleora_ctx *c)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -577,20 +611,12 @@ void cleora_destroy(cleora_ctx *c)
     try {
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
-        DevBuf *bufs[] = {&c->rp,          &c->col,         &c->val,        &c->deg,
-                          &c->E[0],        &c->E[1],        &c->split_items, &c->bucket_row,
-                          &c->long_rows,   &c->chunk_base,  &c->partial,    &c->desc,
-                          &c->blk_norms,   &c->chunk_ids,   &c->chunk_occ,  &c->t_local,
-                          &c->t_expand,    &c->t_edges,     &c->t_wts,      &c->t_cnt,
-                          &c->t_off,       &c->t_keys,      &c->t_tmp,      &c->t_head,
-                          &c->t_pos,       &c->t_esum,      &c->t_lists,    &c->t_scan,
-                          &c->t_small,     &c->multi_desc,  &c->slice_desc, &c->slice_norms};
         drop_graphs(c);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
         if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
         if (c->ev_join) (void)hipEventDestroy(c->ev_join);
-        for (DevBuf *b : bufs) b->release();
+        for (DevBuf *b : cleora::ctx_buffers(c)) b->release();
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->h_small) (void)hipHostFree(c->h_small);
     } catch (...) {

@@ -13,16 +13,20 @@
 // asynchronous copies of each member's rows to its output buffer.  A
 // block-diagonal build gives every member the same bits as building it
 // alone, so grouping changes speed, not results.  A slot is reused only
-// after its result copies have completed.
+// after its result copies have completed.  Which requests form a group,
+// on which slot, and what device memory that is charged is decided by the
+// host-only policy of admission.hpp.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
 
+#include "admission.hpp"
 #include "internal.hpp"
 
 namespace {
@@ -31,7 +35,7 @@ struct SReq {
     int64_t ticket = 0;
     cleora_request r{};
     double submit_s = 0, admit_s = -1, ready_s = -1, done_s = -1;
-    int64_t footprint = 0;
+    int64_t footprint = 0;  // charge: cleora_footprint_bytes plus staging
     int64_t row0 = 0;  // first row inside its group's block-diagonal graph
     int32_t status = CLEORA_OK;
     bool on_dev[3] = {false, false, false};  // src, dst, w in device memory
@@ -88,6 +92,12 @@ struct HostBuf {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Staging bytes a request adds to its group's buffer: src, dst and weights
+// (4 bytes each per edge), its three table entries and the 256-byte
+// alignment of the three arrays (a group's staging never exceeds the sum
+// over its members).
+int64_t staging_bytes(int64_t n_edges) { return 12 * n_edges + 1024; }
+
 }  // namespace
 
 struct cleora_server {
@@ -98,13 +108,14 @@ struct cleora_server {
     int64_t budget = 0;
     std::vector<cleora_ctx *> ctxs;
     std::vector<cleora::DevBuf> staging;  // per slot: the group's edges and tables
-    std::deque<int> free_slots;
+    std::unique_ptr<cleora::Admission> policy;  // queue, slots and memory charges
+    int64_t bound_exceeded = 0;  // builds that held more than they were charged
 
     std::mutex mu;
     std::condition_variable cv_sched, cv_build, cv_done;
-    std::deque<SReq *> pending, done;
+    std::deque<SReq *> pending, done;  // pending mirrors the policy's queue
     std::vector<Group *> building, ready;
-    int64_t used = 0, peak = 0, next_ticket = 0, in_system = 0;
+    int64_t next_ticket = 0, in_system = 0;
     bool stop = false;
     std::string fatal;
 
@@ -112,7 +123,7 @@ struct cleora_server {
     std::vector<Group *> active;
     std::vector<std::pair<hipEvent_t, Group *>> retiring;
     std::vector<hipEvent_t> ev_pool;
-    int64_t steps = 0, stepped = 0, groups = 0;
+    int64_t steps = 0, stepped = 0;
     int32_t max_active = 0;
 
     std::thread sched;
@@ -130,9 +141,7 @@ struct cleora_server {
             q->done_s = t;
             done.push_back(q);
         }
-        used -= g->footprint;
-        // most recently used first: its buffers are already grown
-        free_slots.push_front(g->slot);
+        policy->release(g->slot);
         delete g;
         cv_done.notify_all();
         cv_build.notify_one();
@@ -278,12 +287,23 @@ struct cleora_server {
         HostBuf host;
         for (;;) {
             Group *g = nullptr;
+            cleora::AdmitDecision dec;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_build.wait(lk, [&] { return stop || can_admit_locked(); });
+                cv_build.wait(lk, [&] { return stop || policy->can_admit(); });
                 if (stop) return;
-                g = admit_locked();
+                dec = policy->admit();
+                g = take_group_locked(dec);
                 building.push_back(g);
+            }
+            if (!dec.trim.empty()) {
+                // idle slots give their buffers back to make room (nothing
+                // runs on them: a slot is freed after its last copy ended)
+                for (int t : dec.trim) release_slot(t);
+                std::lock_guard<std::mutex> lk(mu);
+                for (int t : dec.trim)
+                    if (t != g->slot) policy->trimmed(t);
+                cv_build.notify_all();
             }
             int32_t status = CLEORA_OK;
             try {
@@ -317,7 +337,9 @@ struct cleora_server {
                 }
                 if (!bad.empty()) cv_done.notify_all();
             }
+            const int64_t held = slot_bytes(g->slot);
             std::lock_guard<std::mutex> lk(mu);
+            if (!policy->built(g->slot, held)) ++bound_exceeded;
             building.erase(std::find(building.begin(), building.end(), g));
             g->status = status;
             const double t = seconds_since(t0);
@@ -346,36 +368,32 @@ struct cleora_server {
         return e;
     }
 
-    bool can_admit_locked() const
-    {
-        return !pending.empty() && !free_slots.empty() && used + pending.front()->footprint <= budget;
-    }
-
-    // One group, formed when a builder is free to build it: the longest
-    // run of waiting requests (in arrival order, at most max_group) whose
-    // footprints fit the budget.  Forming groups this late lets them grow
-    // with the backlog instead of queueing small groups for the builders.
-    Group *admit_locked()
+    // The group the policy formed: the first dec.count waiting requests.
+    Group *take_group_locked(const cleora::AdmitDecision &dec)
     {
         Group *g = new Group();
-        int64_t n_total = 0;
-        while (!pending.empty() && (int32_t)g->members.size() < max_group) {
+        const double t = seconds_since(t0);
+        for (int32_t i = 0; i < dec.count; ++i) {
             SReq *q = pending.front();
-            if (used + g->footprint + q->footprint > budget ||
-                (!g->members.empty() && n_total + q->r.n_nodes > 0x7fffffffLL))
-                break;
             pending.pop_front();
-            q->admit_s = seconds_since(t0);
+            q->admit_s = t;
             g->members.push_back(q);
-            g->footprint += q->footprint;
-            n_total += q->r.n_nodes;
         }
-        g->slot = free_slots.front();
-        free_slots.pop_front();
-        used += g->footprint;
-        peak = std::max(peak, used);
-        ++groups;
+        g->slot = dec.slot;
+        g->footprint = dec.footprint;
         return g;
+    }
+
+    // Device bytes slot `i` holds: its context's buffers and its staging.
+    int64_t slot_bytes(int i)
+    {
+        return cleora::ctx_device_bytes(ctxs[i]) + (int64_t)staging[i].cap;
+    }
+
+    void release_slot(int i)
+    {
+        cleora::release_buffers(ctxs[i]);
+        staging[i].release();
     }
 
     void sched_loop()
@@ -478,6 +496,7 @@ struct cleora_server {
                     q->done_s = t;
                     done.push_back(q);
                 }
+                policy->drop_front(pending.size());
                 pending.clear();
                 stop = true;
                 cv_build.notify_all();
@@ -521,10 +540,10 @@ int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t d
         rc = cleora_create(&c, device);
         if (rc == CLEORA_OK) {
             s->ctxs.push_back(c);
-            s->free_slots.push_back(i);
         }
     }
     s->staging.resize(s->ctxs.size());
+    for (cleora::DevBuf &b : s->staging) b.exact = true;
     if (rc == CLEORA_OK && hipSetDevice(device) != hipSuccess) rc = CLEORA_E_DEVICE;
     if (rc == CLEORA_OK && budget_bytes == 0) {
         // 80% of what is free on the device now
@@ -532,6 +551,21 @@ int cleora_server_create(cleora_server **out, int device, int32_t dim, int32_t d
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) rc = CLEORA_E_DEVICE;
         else s->budget = (int64_t)(0.8 * (double)free_b);
         if (rc == CLEORA_OK && s->budget < 1) rc = CLEORA_E_NOMEM;
+    }
+    if (rc == CLEORA_OK) {
+        try {
+            s->policy.reset(new cleora::Admission(slots, s->budget, max_group));
+            for (int32_t i = 0; i < slots; ++i) {
+                cleora_ctx *c = s->ctxs[i];
+                cleora::set_exact_growth(c);
+                // the step's descriptor table for every slot, at its final
+                // size, so that stepping allocates nothing
+                c->multi_desc.ensure(sizeof(cleora::StepDesc) * (size_t)slots);
+                s->policy->set_idle_held(i, s->slot_bytes(i));
+            }
+        } catch (const cleora::Error &e) {
+            rc = e.code;
+        }
     }
     if (rc == CLEORA_OK && hipStreamCreateWithFlags(&s->main_s, hipStreamNonBlocking) != hipSuccess)
         rc = CLEORA_E_DEVICE;
@@ -567,7 +601,8 @@ int cleora_server_submit(cleora_server *s, const cleora_request *req, int64_t *t
         return CLEORA_E_INVAL;
     }
     const int64_t fp =
-        (int64_t)cleora_footprint_bytes(req->n_nodes, req->n_edges, s->flags, s->dim, s->dtype);
+        (int64_t)cleora_footprint_bytes(req->n_nodes, req->n_edges, s->flags, s->dim, s->dtype) +
+        staging_bytes(req->n_edges);
     if (fp > s->budget) {
         cleora::set_last_error("request footprint exceeds the whole budget");
         return CLEORA_E_INVAL;
@@ -588,6 +623,7 @@ int cleora_server_submit(cleora_server *s, const cleora_request *req, int64_t *t
     }
     q->ticket = s->next_ticket++;
     q->submit_s = seconds_since(s->t0);
+    s->policy->push(fp, req->n_nodes);
     s->pending.push_back(q);
     s->in_system++;
     s->cv_build.notify_one();
@@ -634,9 +670,24 @@ int cleora_server_stats(cleora_server *s, int64_t *steps, int64_t *stepped, int3
     if (steps) *steps = s->steps;
     if (stepped) *stepped = s->stepped;
     if (max_active) *max_active = s->max_active;
-    if (peak_bytes) *peak_bytes = s->peak;
-    if (groups) *groups = s->groups;
+    if (peak_bytes) *peak_bytes = s->policy->peak();
+    if (groups) *groups = s->policy->groups();
     if (in_system) *in_system = s->in_system;
+    return CLEORA_OK;
+}
+
+int cleora_server_memory(cleora_server *s, int64_t *budget, int64_t *charged, int64_t *peak,
+                         int64_t *bound_exceeded)
+{
+    if (!s) {
+        cleora::set_last_error("NULL server");
+        return CLEORA_E_INVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (budget) *budget = s->policy->budget();
+    if (charged) *charged = s->policy->used();
+    if (peak) *peak = s->policy->peak();
+    if (bound_exceeded) *bound_exceeded = s->bound_exceeded;
     return CLEORA_OK;
 }
 

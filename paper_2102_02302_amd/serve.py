@@ -1,31 +1,23 @@
 """Served form: continuous batching of independent embedding requests.
 
 Each request is a whole graph to embed (T_k of Algorithm 1 for its own
-graph and seed).  The server
+graph and seed).  Serving is the library's native server
+(``cleora_server_*``, wrapped by ``NativeServer``): requests are admitted
+in arrival order as groups built together as one block-diagonal graph,
+while a slot is free and the device memory charged to the slots stays
+within a budget; built groups advance one iteration per step in shared
+launches and retire after k iterations.  Its admission and grouping policy
+is host-only C++ (``csrc/admission.hpp``), unit-tested on the CPU.
 
-* admits waiting requests in arrival order while a slot (a library context)
-  is free and the HBM footprint of everything admitted stays within a
-  budget (``cleora_footprint_bytes``);
-* builds an admitted request's CSR and T_0 on a side stream, in a builder
-  thread, while the running requests keep stepping;
-* advances every running request by one iteration per step, all of them in
-  the same kernel launches (``cleora_step_multi``), whatever iteration each
-  is at: a request joins at the next iteration boundary after its build and
-  leaves as soon as it has done its k iterations, freeing its slot and its
-  share of the budget;
-* records latency = completion - arrival per request.
-
-The scheduling policy (``Scheduler``) is plain Python and is tested on the
-CPU with a simulated engine; ``GpuEngine`` is the MI355X implementation.
+This module drives that server over a request trace (``run_native``),
+serves the same trace one request at a time with the plain path as the
+baseline (``one_at_a_time``), and summarises latencies (``latency_stats``).
 """
 
 from __future__ import annotations
 
-import collections
 import ctypes
 import dataclasses
-import queue
-import threading
 import time
 from typing import Callable, Dict, List, Optional, Sequence
 
@@ -49,202 +41,6 @@ class Job:
     @property
     def latency_s(self) -> float:
         return self.done_s - self.arrival_s
-
-
-class Scheduler:
-    """Admission and iteration-level batching, independent of the device.
-
-    ``engine`` provides: footprint(job) -> bytes; start_build(job, slot)
-    (asynchronous); poll_ready() -> list of jobs whose build finished;
-    step(jobs) (one iteration each, synchronous); start_finish(job)
-    (asynchronous copy of the result); poll_finished() -> list of jobs whose
-    result is out; idle_wait(seconds)."""
-
-    def __init__(self, engine, k: int, max_slots: int, budget_bytes: int,
-                 clock: Callable[[], float] = time.perf_counter):
-        self.engine = engine
-        self.k = k
-        self.max_slots = max_slots
-        self.budget = budget_bytes
-        self.clock = clock
-        self.used = 0
-        self.peak_used = 0
-        self.max_active = 0
-        self.steps = 0
-        self.step_sizes: List[int] = []
-
-    def run(self, jobs: Sequence[Job]) -> List[Job]:
-        jobs = sorted(jobs, key=lambda j: (j.arrival_s, j.index))
-        for j in jobs:
-            j.footprint = int(self.engine.footprint(j))
-            if j.footprint > self.budget:
-                raise ValueError(f"request {j.index} needs {j.footprint} bytes, "
-                                 f"more than the whole budget {self.budget}")
-        free_slots = collections.deque(range(self.max_slots))
-        pending: collections.deque = collections.deque()
-        building: Dict[int, Job] = {}
-        retiring: Dict[int, Job] = {}
-        active: List[Job] = []
-        done: List[Job] = []
-        nxt = 0
-        t0 = self.clock()
-        while len(done) < len(jobs):
-            now = self.clock() - t0
-            while nxt < len(jobs) and jobs[nxt].arrival_s <= now:
-                pending.append(jobs[nxt])
-                nxt += 1
-            # admission: arrival order, a free slot, and the budget
-            while pending and free_slots and self.used + pending[0].footprint <= self.budget:
-                j = pending.popleft()
-                j.slot = free_slots.popleft()
-                j.admitted_s = self.clock() - t0
-                self.used += j.footprint
-                self.peak_used = max(self.peak_used, self.used)
-                building[j.index] = j
-                self.engine.start_build(j, j.slot)
-            for j in self.engine.poll_finished():
-                retiring.pop(j.index)
-                j.done_s = self.clock() - t0
-                self.used -= j.footprint
-                free_slots.append(j.slot)
-                done.append(j)
-            for j in self.engine.poll_ready():
-                building.pop(j.index)
-                j.ready_s = self.clock() - t0
-                if self.k == 0:
-                    retiring[j.index] = j
-                    self.engine.start_finish(j)
-                else:
-                    active.append(j)
-            if active:
-                self.max_active = max(self.max_active, len(active))
-                self.engine.step(active)
-                self.steps += 1
-                self.step_sizes.append(len(active))
-                still = []
-                for j in active:
-                    j.iteration += 1
-                    if j.iteration >= self.k:
-                        retiring[j.index] = j
-                        self.engine.start_finish(j)
-                    else:
-                        still.append(j)
-                active = still
-            else:
-                wait = 0.0002 if (building or retiring) else 0.0005
-                if nxt < len(jobs) and not building and not pending and not retiring:
-                    wait = max(0.0, min(0.01, jobs[nxt].arrival_s - (self.clock() - t0)))
-                self.engine.idle_wait(wait)
-        return done
-
-
-class GpuEngine:
-    """Requests on one MI355X: one library context per slot (reused, so its
-    device buffers are reused), builds on a side stream in a worker thread,
-    steps with ``step_multi`` on the main stream."""
-
-    def __init__(self, dim: int, dtype: str, max_slots: int, device: int = 0,
-                 keep_results: bool = False, builders: int = 4):
-        import torch
-
-        from . import Context, footprint_bytes
-        self.torch = torch
-        self.dim, self.dtype = dim, dtype
-        self.keep_results = keep_results
-        self._footprint = footprint_bytes
-        self.ctxs = [Context(device) for _ in range(max_slots)]
-        self.main = torch.cuda.Stream(device=device)
-        self._todo: queue.Queue = queue.Queue()
-        self._ready: queue.Queue = queue.Queue()
-        self._err: Optional[BaseException] = None
-        self._retiring: list = []
-        # several builders, each with its own stream, so that the host-side
-        # latency of one build (launches, two synchronisations) overlaps others
-        self._workers = []
-        for _ in range(max(1, builders)):
-            t = threading.Thread(target=self._build_loop,
-                                 args=(torch.cuda.Stream(device=device),), daemon=True)
-            t.start()
-            self._workers.append(t)
-
-    def footprint(self, job: Job) -> int:
-        g = job.payload
-        return self._footprint(job.n, job.m, self.dim, self.dtype, directed=g.directed)
-
-    def start_build(self, job: Job, slot: int) -> None:
-        self._todo.put(job)
-
-    def _build_loop(self, side) -> None:
-        torch = self.torch
-        while True:
-            job = self._todo.get()
-            if job is None:
-                return
-            try:
-                ctx = self.ctxs[job.slot]
-                g = job.payload
-                with torch.cuda.stream(side):
-                    ctx.build_csr(g.n, g.src, g.dst, g.w, directed=g.directed, stream=side)
-                    ctx.init(self.dim, self.dtype, job.seed, stream=side)
-                    ctx.sync(side)
-                self._ready.put(job)
-            except BaseException as e:  # surfaced by poll_ready
-                self._err = e
-                self._ready.put(None)
-
-    def poll_ready(self) -> List[Job]:
-        out = []
-        while True:
-            try:
-                j = self._ready.get_nowait()
-            except queue.Empty:
-                break
-            if j is None:
-                raise RuntimeError("request build failed") from self._err
-            out.append(j)
-        return out
-
-    def step(self, jobs: List[Job]) -> None:
-        from . import step_multi
-        step_multi([self.ctxs[j.slot] for j in jobs], stream=self.main)
-
-    def start_finish(self, job: Job) -> None:
-        """Copy the result to pinned host memory on the copy stream; the
-        slot is released when the copy's event has completed."""
-        torch = self.torch
-        ctx = self.ctxs[job.slot]
-        inf = ctx.info()
-        tdt = torch.float32 if inf["dtype"] == 0 else torch.bfloat16
-        host = torch.empty((inf["n"], inf["dim"]), dtype=tdt, pin_memory=True)
-        from . import _lib
-        _lib.check(ctx._lib.cleora_get_embedding(ctx.handle, host.data_ptr(), inf["dim"],
-                                                 inf["dtype"], ctypes.c_void_p(self.main.cuda_stream)))
-        ev = torch.cuda.Event()
-        ev.record(self.main)
-        self._retiring.append((ev, job, host))
-
-    def poll_finished(self) -> List[Job]:
-        out, keep = [], []
-        for ev, job, host in self._retiring:
-            if ev.query():
-                job.result = host if self.keep_results else None
-                out.append(job)
-            else:
-                keep.append((ev, job, host))
-        self._retiring = keep
-        return out
-
-    def idle_wait(self, seconds: float) -> None:
-        if seconds > 0:
-            time.sleep(seconds)
-
-    def close(self) -> None:
-        for _ in self._workers:
-            self._todo.put(None)
-        for t in self._workers:
-            t.join(timeout=10)
-        for c in self.ctxs:
-            c.close()
 
 
 def one_at_a_time(jobs: Sequence[Job], dim: int, k: int, dtype: str = "f32", device: int = 0,
@@ -307,8 +103,8 @@ def latency_stats(done: Sequence[Job], k: int, dim: int, nnz_of: Callable[[Job],
 
 
 class NativeServer:
-    """The C++ request server of the library (``cleora_server_*``): the same
-    policy as ``Scheduler``, with native scheduler and builder threads."""
+    """The C++ request server of the library (``cleora_server_*``): native
+    builder and scheduler threads, admission by charged device memory."""
 
     def __init__(self, dim: int, dtype: str, k: int, slots: int = 64,
                  budget_bytes: int = 64 << 30, builders: int = 3, device: int = 0,
@@ -364,7 +160,16 @@ class NativeServer:
                                                   ctypes.byref(c), ctypes.byref(d),
                                                   ctypes.byref(e), ctypes.byref(f)))
         return {"steps": a.value, "request_steps": b.value, "max_active_groups": c.value,
-                "peak_footprint_bytes": d.value, "groups": e.value, "in_system": f.value}
+                "peak_charged_bytes": d.value, "groups": e.value, "in_system": f.value}
+
+    def memory(self) -> dict:
+        """Budget, bytes charged now and at most, and builds whose slot held
+        more than it was charged (0 when every footprint bounded its build)."""
+        a, b, c, d = (ctypes.c_int64() for _ in range(4))
+        self._check(self._lib.cleora_server_memory(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                   ctypes.byref(c), ctypes.byref(d)))
+        return {"budget_bytes": a.value, "charged_bytes": b.value, "peak_charged_bytes": c.value,
+                "bound_exceeded": d.value}
 
     def close(self) -> None:
         if getattr(self, "_h", None):

@@ -29,29 +29,54 @@ def jobs_for(trace, graphs, time_scale):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_served_results_equal_solo(cl, dtype):
-    from paper_2102_02302_amd.serve import GpuEngine, Scheduler, latency_stats
+    """Poisson arrivals about every 0.5 ms: requests join while others step,
+    and every result equals the request embedded alone, bit for bit, and is
+    within the stated tolerance of the FP64 oracle."""
+    from paper_2102_02302_amd.serve import latency_stats, run_native
     trace = gen.served_trace(24, 1.0, n_lo=100, n_hi=20_000)
     graphs = gen.materialize(trace)
     dim, k = 64, 4
-    jobs = jobs_for(trace, graphs, 0.0005)  # arrivals every ~0.5 ms on average
-    eng = GpuEngine(dim, dtype, max_slots=6, keep_results=True)
-    try:
-        sched = Scheduler(eng, k=k, max_slots=6, budget_bytes=1 << 30)
-        done = sched.run(jobs)
-    finally:
-        eng.close()
+    jobs = jobs_for(trace, graphs, 0.0005)
+    done = run_native(jobs, dim, dtype, k, slots=6, budget_bytes=1 << 30, builders=2,
+                      keep_results=True, max_group=4)
     assert len(done) == len(jobs)
-    assert sched.max_active >= 2, "requests never overlapped"
-    stats = latency_stats(done, k, dim, lambda j: 2 * j.m)
-    print(f"{dtype}: {stats}, max active {sched.max_active}")
+    st = run_native.last_stats
+    assert st["max_active_groups"] >= 2, "requests never overlapped"
+    print(f"{dtype}: {latency_stats(done, k, dim, lambda j: 2 * j.m)}, {st}")
     for j in done:
         g = j.payload
-        solo = cl.embed(g, dim, k, j.seed, dtype=dtype).float().cpu().numpy()
-        got = j.result.float().numpy()
-        assert np.array_equal(got, solo), j.index
+        solo = cl.embed(g, dim, k, j.seed, dtype=dtype)
+        assert torch_equal(j.result, solo), j.index
         want = oracle.embed(g, dim, k, j.seed)
-        err = np.abs(got - want).max()
+        err = np.abs(j.result.float().cpu().numpy() - want).max()
         assert err <= (1e-5 if dtype == "f32" else 4e-3), (j.index, err)
+
+
+def test_native_server_memory_within_budget(cl):
+    """A budget of about 2.5 of the largest request's charge: idle slots give
+    their buffers back to make room, the charged memory never exceeds the
+    budget, every build stays within its charge, and results are still
+    those of the requests embedded alone."""
+    from paper_2102_02302_amd.serve import NativeServer, run_native
+    trace = gen.served_trace(40, 1.0, n_lo=100, n_hi=30_000)
+    graphs = gen.materialize(trace)
+    dim, k = 64, 4
+    charge = [cl.footprint_bytes(g.n, g.m, dim, "f32") + 12 * g.m + 1024 for g in graphs]
+    budget = int(2.5 * max(charge))
+    srv = NativeServer(dim, "f32", k, slots=6, budget_bytes=budget, builders=2, max_group=4)
+    try:
+        done = run_native(jobs_for(trace, graphs, 0.0002), dim, "f32", k, keep_results=True,
+                          server=srv)
+        mem = srv.memory()
+    finally:
+        srv.close()
+    print(f"budget {budget}: {mem}, {run_native.last_stats}")
+    assert len(done) == len(graphs)
+    assert mem["budget_bytes"] == budget
+    assert mem["peak_charged_bytes"] <= budget
+    assert mem["bound_exceeded"] == 0
+    for j in done[::5]:
+        assert torch_equal(j.result, cl.embed(j.payload, dim, k, j.seed)), j.index
 
 
 def test_one_at_a_time_baseline(cl):
