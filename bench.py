@@ -453,7 +453,7 @@ def parse():
                     help="override the workload's d (e.g. one GPU's share of the columns)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--slices", type=int, default=0,
-                    help="run each iteration as column slices this wide (FP32; 0: whole rows)")
+                    help="run each iteration as column slices this wide (0: whole rows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's schedule autotuner (run once per graph "
@@ -583,7 +583,7 @@ def main():
         ctx.set_slices(args.slices)
 
     main_run = _measure(ctx, g, src, dst, w, dim, k, dtype, args.steps, args.warmup,
-                        args.slices, not args.no_autotune, args.workload,
+                        not args.no_autotune, args.workload,
                         traffic_ok=dim == spec["dim"])
     n, nnz = main_run["n"], main_run["nnz"]
     out = {
@@ -606,6 +606,7 @@ def main():
                    "parallelism": "single GPU"},
         "propagate_only": main_run["propagate_only"],
         "phases_ms": main_run["phases_ms"],
+        "launch_path": main_run["launch_path"],
         "roofline": main_run["roofline"],
     }
     # the other storage type beside the headline (same graph, same GPU)
@@ -614,7 +615,7 @@ def main():
     if other and other != dtype and args.steps > 0:
         o_steps = max(3, args.steps // 2)
         o = _measure(ctx, g, src, dst, w, dim, k, other, o_steps, max(1, args.warmup // 2),
-                     args.slices, not args.no_autotune, args.workload,
+                     not args.no_autotune, args.workload,
                      traffic_ok=dim == spec["dim"])
         out[other] = {"value": o["value"], "unit": "GEdge-dims/s", "steps": o_steps,
                       "ms_per_step": o["ms_per_step"],
@@ -628,7 +629,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, slices, autotune, workload,
+def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, autotune, workload,
              traffic_ok) -> dict:
     """Timed steps of the whole path in one storage type, then the phases
     one by one (untimed by the headline), and the roofline of the SpMM."""
@@ -648,14 +649,32 @@ def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, slices, autotune
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    ctx.kernel_time()  # reset
-    ctx.set_timing(True)
-    torch.cuda.synchronize()
+    # the timed steps: the production launch path (k iterations as one
+    # captured graph, reused from step to step), with HIP events on the
+    # launch stream around each graph replay
+    launches0 = ctx.launch_stats()
+    loop_events = []
     t_start = time.perf_counter()
     for _ in range(steps):
-        step()
+        ctx.build_init(g.n, src, dst, w, dim, dtype, seed=2102, directed=g.directed)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.propagate(k)
+        b.record()
+        loop_events.append((a, b))
     torch.cuda.synchronize()
     t_end = time.perf_counter()
+    launches1 = ctx.launch_stats()
+    loop_ms = sum(a.elapsed_time(b) for a, b in loop_events) / max(steps, 1)
+    # kernel durations: the same steps with every SpMM and combine launch
+    # between two HIP events (eager launches of the same kernels and
+    # arguments: events inside a graph carry no time)
+    kernel_steps = max(2, steps // 4)
+    ctx.kernel_time()  # reset
+    ctx.set_timing(True)
+    for _ in range(kernel_steps):
+        step()
+    torch.cuda.synchronize()
     ctx.set_timing(False)
     kt = ctx.kernel_time()
     info = ctx.info()
@@ -683,32 +702,36 @@ def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, slices, autotune
     edge_dims = float(k) * nnz * dim
     value = edge_dims / (ms_per_step * 1e-3) / 1e9
 
-    # dominant kernel: fused SpMM + normalise; with column slices, the S
-    # slice launches of one iteration together (each re-reads col and val)
-    ld = -(-dim * esz // 16) * 16 // esz
-    n_slices = -(-ld // slices) if slices and dtype == "f32" else 1
-    spmm_ms = kt["spmm_ms"] / max(kt["spmm_launches"], 1) * n_slices
-    comb_ms = (kt["combine_ms"] / max(kt["combine_launches"], 1) * n_slices
-               if kt["combine_launches"] else 0.0)
+    # dominant kernel: fused SpMM + normalise, per launch; with column
+    # slices one iteration is S launches, each gathering its slice of the
+    # rows and reading every entry's column index and value
     sched = ctx.schedule()
+    ld = -(-dim * esz // 16) * 16 // esz
+    n_slices = -(-ld // sched["slice_cols"]) if sched["slice_cols"] else 1
+    spmm_ms = kt["spmm_ms"] / max(kt["spmm_launches"], 1)
+    comb_ms = (kt["combine_ms"] / max(kt["combine_launches"], 1)
+               if kt["combine_launches"] else 0.0)
     split_rows = sched["split_rows"]
-    spmm_bytes = n_slices * nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz
+    spmm_bytes = (n_slices * nnz * 8 + nnz * dim * esz + (n - split_rows) * dim * esz) / n_slices
     # compulsory bytes: every entry's index and value once, every row of
     # T_{t-1} read once and every finished row of T_t written once
-    compulsory = nnz * 8 + n * dim * esz + (n - split_rows) * dim * esz
+    compulsory = (n_slices * nnz * 8 + n * dim * esz + (n - split_rows) * dim * esz) / n_slices
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     # the counter summaries are of the workload's own d
     traffic = _traffic(workload, dtype) if traffic_ok else None
-    # with slices an iteration also zeroes, inverts and scales: take the
-    # separately timed propagate call instead of the SpMM launches
-    iter_ms = spmm_ms + comb_ms if n_slices == 1 else phase["propagate_ms"] / k
+    # one iteration on the production path: the captured loop's time over k
+    iter_ms = loop_ms / max(k, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_spmm_norm" if n_slices == 1 else
-                          f"k_spmm_norm, {n_slices} column slices per iteration (figures per iteration)",
+                          f"k_spmm_norm, one of {n_slices} column slices of "
+                          f"{sched['slice_cols']} per iteration (figures per launch)",
                 "bytes_per_launch": int(spmm_bytes),
                 "avg_launch_ms": round(spmm_ms, 4), "launches": kt["spmm_launches"],
+                "kernel_timing": f"HIP events around each launch over {kernel_steps} steps "
+                                 f"after the timed ones",
                 "combine_avg_ms": round(comb_ms, 4),
+                "graph_iteration_ms": round(loop_ms / max(k, 1), 4),
                 "compulsory_bytes_per_launch": int(compulsory),
                 "compulsory_frac": round(compulsory / (spmm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "schedule": sched, "autotune": tuned}
@@ -719,6 +742,10 @@ def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, slices, autotune
     model_it = nnz * 8 + nnz * dim * esz + n * dim * esz
     return {"n": n, "nnz": nnz, "value": round(value, 3), "ms_per_step": round(ms_per_step, 3),
             "n_slices": n_slices,
+            "launch_path": {"graph_replays": launches1["graph_launches"] - launches0["graph_launches"],
+                            "graph_instantiations": launches1["graph_instantiations"]
+                            - launches0["graph_instantiations"],
+                            "loop_ms_per_step": round(loop_ms, 4)},
             "propagate_only": {"ms_per_iteration": round(iter_ms, 4),
                                "gedge_dims_per_s": round(nnz * dim / (iter_ms * 1e-3) / 1e9, 2),
                                "model_bytes_per_iteration": int(model_it),

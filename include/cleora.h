@@ -208,11 +208,11 @@ int cleora_info(cleora_ctx *ctx, int64_t *n_nodes, int64_t *nnz, int32_t *dim, i
 /* Propagation schedule planned by the last cleora_init: split size, number
  * of split pieces, rows split into pieces (finished by the combine step),
  * packed work items, packing size, SpMM grid (0: one wave per work item,
- * m: m x the resident waves).  Any pointer may be NULL.
- * Errors: E_STATE (no embedding). */
+ * m: m x the resident waves), column-slice width (0: whole rows).  Any
+ * pointer may be NULL.  Errors: E_STATE (no embedding). */
 int cleora_schedule_info(cleora_ctx *ctx, int32_t *chunk, int64_t *n_split_chunks,
                          int64_t *n_split_rows, int64_t *n_packed_items, int32_t *pack,
-                         int32_t *persistent);
+                         int32_t *persistent, int32_t *slice_cols);
 
 /* Wait for the stream.  Errors: E_DEVICE. */
 int cleora_sync(cleora_ctx *ctx, void *stream);
@@ -227,21 +227,27 @@ int cleora_sync(cleora_ctx *ctx, void *stream);
  * Errors: E_INVAL (chunk < 0 or > 2^20). */
 int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
 
-/* Run the iterations of the next cleora_init, cleora_build_init or
- * cleora_embed_batch on this context as column slices `cols` wide (0, the
- * default: whole rows).  Float32 embeddings only; a CLEORA_BF16 context
- * ignores it.  Each slice's SpMM gathers that part of the neighbour rows
- * (a narrower gather keeps more of the most-used rows of T in cache),
- * stores its rows unscaled and adds its share of each row's squared norm;
- * then every row is scaled by 1/norm (Section 3.2's normalisation, over
- * the whole row), so T_t is complete after each iteration.  Results differ
- * from whole rows in float32 rounding only (a narrow slice may gather
- * several entries at once in lane groups, and each squared norm is summed
- * slice by slice); with cols >= the padded row width (one slice) they are
- * the same bits.  Propagate resumption, graph replay and batch = solo (with
- * the same setting) hold as before.
- * cleora_step_multi and cleora_propagate_rows use whole rows.
- * Errors: E_INVAL (cols < 0, not a multiple of 4, or above 4096). */
+/* Column slices of the iterations, taking effect at the next cleora_init,
+ * cleora_build_init or cleora_embed_batch on this context: cols = 0 (the
+ * default) keeps whole rows, cols > 0 slices `cols` wide (rounded up to
+ * 16 bytes for CLEORA_BF16; at least the padded row width: whole rows).
+ * Each slice's SpMM gathers that part of the neighbour rows (a narrower
+ * gather keeps more of the most-used rows of T in cache), stores its rows
+ * unscaled and adds its share of each row's squared norm (Section 3.2's
+ * normalisation is over the whole row).  The next iteration multiplies by
+ * M diag(1/norm) (M's values scaled per column, one pass over them)
+ * instead of scaling the rows, and each cleora_propagate call ends by
+ * writing the normalised T_k out of place; the unscaled rows stay for the
+ * next call.  Results differ from whole rows in rounding only (with
+ * CLEORA_BF16 the stored rows are unscaled bfloat16 and T_k is rounded
+ * once more when it is written); propagate resumption, graph replay and
+ * batch = solo (with the same setting) hold bit for bit.  While the
+ * unscaled rows are kept, T_{t-1} is not: cleora_previous_embedding_ptr
+ * returns E_STATE.  cleora_step_multi steps whole rows from the normalised
+ * T_t, and cleora_autotune's trial steps discard the unscaled rows: the
+ * context continues from the normalised T_t.  cleora_propagate_rows uses
+ * whole rows.  Errors: E_INVAL (cols < 0, not a multiple of 4, or above
+ * 8192). */
 int cleora_set_slices(cleora_ctx *ctx, int32_t cols);
 
 /* Fix the propagation schedule instead of the autotuned or default one
@@ -271,25 +277,23 @@ int cleora_set_schedule(cleora_ctx *ctx, int32_t pack, int32_t persistent);
 int cleora_autotune(cleora_ctx *ctx, int32_t *pack, int32_t *persistent, float *step_ms,
                     void *stream);
 
-/* Kernel timing for measurement: when on, the library records HIP events
- * around every SpMM+normalise (and combine) launch on the launch stream --
- * inside the captured graph when k >= 2 iterations run as one, so timed
- * runs take the same launch path as untimed ones -- and accumulates their
- * durations; cleora_kernel_time returns the total milliseconds and the
- * number of launches timed since the last reset (and resets).  A graph's
- * events are read before its next replay (which then waits for the
- * previous one) or by cleora_kernel_time (which waits for the device
- * work). */
+/* Kernel timing for measurement: when on, the library launches every
+ * iteration eagerly (not as a captured graph: events recorded inside a
+ * graph carry no time) and records HIP events around every SpMM+normalise
+ * and combine launch on the launch stream, accumulating their durations;
+ * cleora_kernel_time returns the total milliseconds and the number of
+ * launches timed since the last reset (and resets).  The kernels and their
+ * arguments are those of the captured graph. */
 int cleora_set_timing(cleora_ctx *ctx, int on);
 int cleora_kernel_time(cleora_ctx *ctx, double *spmm_ms, int64_t *spmm_launches,
                        double *combine_ms, int64_t *combine_launches);
 
 /* Launch statistics since the context was created: captured k-iteration
- * graphs instantiated, and graph replays.  k >= 2 iterations run as one
- * captured graph, kept per (k, starting buffer, timing) together with the
- * launch parameters it was captured with; a later call replays it whenever
- * those are unchanged (e.g. a graph of the same shape rebuilt into the
- * same buffers) and captures anew otherwise.  Any pointer may be NULL.
+ * graphs instantiated, and graph replays.  k >= 2 iterations (without
+ * timing) run as one captured graph, kept per (k, starting buffer) together
+ * with the launch parameters it was captured with; a later call replays it
+ * whenever those are unchanged (e.g. a graph of the same shape rebuilt into
+ * the same buffers) and captures anew otherwise.  Any pointer may be NULL.
  * Errors: E_INVAL (NULL ctx). */
 int cleora_launch_stats(cleora_ctx *ctx, int64_t *graph_instantiations, int64_t *graph_launches);
 

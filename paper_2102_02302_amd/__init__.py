@@ -145,9 +145,9 @@ class Context:
         _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
 
     def set_slices(self, cols: int) -> None:
-        """Run the iterations of the next init as column slices ``cols`` wide
-        (0: whole rows); float32 embeddings only (results differ from whole
-        rows in float32 rounding only)."""
+        """Column slices of the next init's iterations: 0 whole rows (the
+        default), else ``cols`` wide (results differ from whole rows in
+        rounding only)."""
         _lib.check(self._lib.cleora_set_slices(self._h, int(cols)))
 
     def set_schedule(self, pack: int = 0, persistent: int = -1) -> None:
@@ -205,13 +205,15 @@ class Context:
                 "iteration": it.value}
 
     def schedule(self) -> dict:
-        chunk, pack, persist = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        chunk, pack, persist, sl = (ctypes.c_int32() for _ in range(4))
         ns, nl, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.check(self._lib.cleora_schedule_info(self._h, ctypes.byref(chunk), ctypes.byref(ns),
                                                   ctypes.byref(nl), ctypes.byref(nb),
-                                                  ctypes.byref(pack), ctypes.byref(persist)))
+                                                  ctypes.byref(pack), ctypes.byref(persist),
+                                                  ctypes.byref(sl)))
         return {"chunk": chunk.value, "split_chunks": ns.value, "split_rows": nl.value,
-                "packed_items": nb.value, "pack": pack.value, "persistent": persist.value}
+                "packed_items": nb.value, "pack": pack.value, "persistent": persist.value,
+                "slice_cols": sl.value}
 
     def embedding(self, dtype=None, stream=None):
         """Copy of the current N x dim embedding as a device tensor."""
@@ -345,7 +347,7 @@ class Context:
 def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
           empty_keep: bool = False, chunk: int = 0, slices: int = 0):
     """Whole path for one graph: build M, initialise T_0, k iterations
-    (``slices``: the column-slice option of float32 iterations, 0 = off)."""
+    (``slices``: the column slices of the iterations, 0 whole rows)."""
     with Context(device) as ctx:
         if chunk:
             ctx.set_chunk(chunk)

@@ -31,7 +31,8 @@ EXPORTS = [
     "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
     "cleora_set_slices",
     "cleora_set_timing",
-    "cleora_kernel_time", "cleora_launch_stats", "cleora_autotune", "cleora_expand_clique", "cleora_expand_star",
+    "cleora_kernel_time", "cleora_launch_stats", "cleora_autotune", "cleora_expand_clique",
+    "cleora_expand_star",
     "cleora_build_chunk", "cleora_chunk_info", "cleora_merge_chunk", "cleora_merge_finish",
     "cleora_embed_batch", "cleora_batch_status", "cleora_step_multi", "cleora_server_create",
     "cleora_server_submit",
@@ -105,7 +106,8 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(i32)]),
         "cleora_schedule_info": (ctypes.c_int, [p, ctypes.POINTER(i32), ctypes.POINTER(i64),
                                                 ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                                ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+                                                ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                                ctypes.POINTER(i32)]),
         "cleora_sync": (ctypes.c_int, [p, p]),
         "cleora_set_chunk": (ctypes.c_int, [p, i32]),
         "cleora_set_schedule": (ctypes.c_int, [p, i32, i32]),

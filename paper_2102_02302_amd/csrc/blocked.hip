@@ -72,6 +72,61 @@ __global__ void k_scale_rows(float4 *__restrict__ E, int64_t n, int32_t vpr,
     }
 }
 
+// One wave per row, out of place: dst row r = src row r times its factor.
+__global__ void k_scale_rows_to(const float4 *__restrict__ src, float4 *__restrict__ dst,
+                                int64_t n, int32_t vpr, const float *__restrict__ inv)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n;
+         r += waves) {
+        const float f = inv[r];
+        const float4 *a = src + r * vpr;
+        float4 *b = dst + r * vpr;
+        for (int32_t j = lane; j < vpr; j += 64) {
+            float4 x = a[j];
+            x.x *= f;
+            x.y *= f;
+            x.z *= f;
+            x.w *= f;
+            b[j] = x;
+        }
+    }
+}
+
+// The same for bfloat16 rows: widened, scaled in float32, rounded to
+// nearest even (eight elements per 16-byte vector).
+__global__ void k_scale_rows_to_bf16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                     int64_t n, int32_t vpr, const float *__restrict__ inv)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n;
+         r += waves) {
+        const float f = inv[r];
+        const uint4 *a = src + r * vpr;
+        uint4 *b = dst + r * vpr;
+        for (int32_t j = lane; j < vpr; j += 64) {
+            const uint4 x = a[j];
+            uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = f32_to_bf16_rne(bf16_lo(w[q]) * f) | (f32_to_bf16_rne(bf16_hi(w[q]) * f) << 16);
+            b[j] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    }
+}
+
+// M diag(inv): every stored value times the factor of its column's row.
+__global__ void k_scale_values(int64_t nnz, const float *__restrict__ val,
+                               const int32_t *__restrict__ col, const float *__restrict__ inv,
+                               float *__restrict__ out)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = val[e] * inv[col[e]];
+}
+
 unsigned grid_for_rows(int64_t n, int per_block)
 {
     return (unsigned)std::min<int64_t>(std::max<int64_t>((n + per_block - 1) / per_block, 1),
@@ -96,6 +151,26 @@ void launch_scale_rows(float *E, int64_t n, int32_t ld, const float *inv, hipStr
 {
     k_scale_rows<<<grid_for_rows(n, 4), 256, 0, s>>>(reinterpret_cast<float4 *>(E), n, ld / 4,
                                                      inv);
+    CLEORA_LAUNCH_CHECK();
+}
+
+void launch_scale_rows_to(int dtype, const void *src, void *dst, int64_t n, int32_t ld,
+                          const float *inv, hipStream_t s)
+{
+    if (dtype == CLEORA_BF16)
+        k_scale_rows_to_bf16<<<grid_for_rows(n, 4), 256, 0, s>>>(
+            reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst), n, ld / 8, inv);
+    else
+        k_scale_rows_to<<<grid_for_rows(n, 4), 256, 0, s>>>(
+            reinterpret_cast<const float4 *>(src), reinterpret_cast<float4 *>(dst), n, ld / 4, inv);
+    CLEORA_LAUNCH_CHECK();
+}
+
+void launch_scale_values(const float *val, const int32_t *col, const float *inv, int64_t nnz,
+                         float *out, hipStream_t s)
+{
+    if (nnz <= 0) return;
+    k_scale_values<<<grid_for_rows(nnz, 256), 256, 0, s>>>(nnz, val, col, inv, out);
     CLEORA_LAUNCH_CHECK();
 }
 

@@ -73,12 +73,17 @@ struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
     bool exact = false;  // grow to the size asked for (no 1.5x step)
+    bool fixed = false;  // a view into memory the buffer does not own: never reallocated
     // A regrowth asks for at least 1.5x the old size (the exact size if
     // that fails, or with `exact`), so a buffer reused for slowly growing
     // sizes reallocates O(log) times: each free waits for the device.
     void ensure(size_t bytes)
     {
         if (bytes <= cap && p) return;
+        if (fixed)
+            throw Error(CLEORA_E_INVAL, "needs " + std::to_string(bytes) +
+                                            " bytes of a fixed scratch region of " +
+                                            std::to_string(cap));
         const size_t grown = cap && !exact ? cap + cap / 2 : 0;
         release();
         size_t b = std::max<size_t>(bytes, 256);
@@ -99,6 +104,7 @@ struct DevBuf {
     }
     void release()
     {
+        if (fixed) return;
         if (p) (void)hipFree(p);
         p = nullptr;
         cap = 0;

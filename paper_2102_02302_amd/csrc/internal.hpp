@@ -128,6 +128,13 @@ void launch_widen_bf16(const void *src, int64_t n, int32_t dim, int32_t ld_src, 
 void launch_fill_zero(float *x, int64_t n, hipStream_t s);
 void launch_inv_norm(const float *ss, float *inv, int64_t n, hipStream_t s);
 void launch_scale_rows(float *E, int64_t n, int32_t ld, const float *inv, hipStream_t s);
+// dst row r = src row r * inv[r] (n x ld, float32 or bfloat16 rounded to
+// nearest even, out of place).
+void launch_scale_rows_to(int dtype, const void *src, void *dst, int64_t n, int32_t ld,
+                          const float *inv, hipStream_t s);
+// out[e] = val[e] * inv[col[e]]: the values of M diag(inv).
+void launch_scale_values(const float *val, const int32_t *col, const float *inv, int64_t nnz,
+                         float *out, hipStream_t s);
 
 }  // namespace cleora
 
@@ -142,10 +149,6 @@ struct LoopGraph {
     std::vector<int64_t> sig;
     hipEvent_t done = nullptr;  // recorded after every replay
     bool launched = false;
-    // timing events recorded by the graph around each launch (captured
-    // with timing on); `unread`: replayed since they were last read
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmm, ev_comb;
-    bool unread = false;
 };
 }  // namespace cleora
 
@@ -174,11 +177,15 @@ struct cleora_ctx {
     cleora::DevBuf split_items, bucket_row, long_rows, chunk_base, partial, desc;
     // column-blocked form: per-row 1/norm of iterations 1..k, squared norms
     cleora::DevBuf blk_norms;
-    // column slices of one iteration (FP32 only; 0: whole rows): requested
-    // width, width in use, the slices' combine descriptors, squared norms
-    // and 1/norm per row
+    // column slices of each iteration (0: whole rows): requested
+    // width, width in use, the slices' combine descriptors,
+    // squared norms and 1/norm per row, and the values of M diag(1/norm)
+    // that the next iteration reads.  `deferred`: E[cur] holds the
+    // normalised T_t and E[cur ^ 1] the unscaled rows it was scaled from,
+    // with their factors in slice_norms (the next iteration reads those).
     int32_t slice_req = 0, slice_cols = 0;
-    cleora::DevBuf slice_desc, slice_norms;
+    bool deferred = false;
+    cleora::DevBuf slice_desc, slice_norms, val2;
 
     // build temporaries (grow-only)
     cleora::DevBuf t_edges, t_wts, t_cnt, t_off, t_keys, t_tmp, t_head, t_pos, t_esum, t_lists,
@@ -188,7 +195,7 @@ struct cleora_ctx {
     // per-graph status of the last cleora_embed_batch call
     std::vector<int32_t> batch_status;
 
-    // captured k-iteration graphs, keyed by (k, starting parity, timing)
+    // captured k-iteration graphs, keyed by (k, starting parity, deferred)
     std::map<std::tuple<int32_t, int, bool>, cleora::LoopGraph> graphs;
     int64_t graph_instantiations = 0, graph_launches = 0;
     hipStream_t cap_stream = nullptr;
@@ -196,14 +203,11 @@ struct cleora_ctx {
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-    // timing: events of eager launches (from a reused pool) and the totals
-    // read so far from those and from captured graphs' events
+    // timing (eager launches between events from a reused pool)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_spmm, ev_comb;
     size_t ev_next = 0;
-    double t_spmm_ms = 0, t_comb_ms = 0;
-    int64_t t_spmm_n = 0, t_comb_n = 0;
 };
 
 namespace cleora {
@@ -235,6 +239,15 @@ void build_group_and_init(cleora_ctx *c, int32_t n_graphs, int64_t n_total, int6
                           const int64_t *d_eoff, const uint64_t *d_seeds, uint32_t flags,
                           int32_t dim, int32_t dtype, hipStream_t s);
 void set_last_error(const std::string &msg);
+// cleora_propagate_rows: argument checks (throwing E_INVAL), and the work on
+// a context whose buffers serve as scratch (synchronises s).
+void check_rows_args(int64_t n_rows, int64_t n_cols, int64_t m, const int32_t *rows,
+                     const int32_t *cols, const void *T_in, int64_t ld_in, int32_t dim,
+                     int32_t dtype, const void *out, int64_t ld_out);
+void propagate_rows_into(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t m,
+                         const int32_t *rows, const int32_t *cols, const float *w,
+                         const void *T_in, int32_t dim, int32_t dtype, void *out, int64_t ld_out,
+                         hipStream_t s);
 // Every device buffer of a context; their summed capacity; exact growth for
 // all of them (the server's memory accounting); release all but the status
 // words (the context then holds no graph and no embedding).

@@ -863,12 +863,13 @@ void write_descs(cleora_ctx *c, hipStream_t s)
     if (c->slice_cols > 0) {
         // column slices: entry p * S + j reads buffer p, columns of slice j
         c->slice_norms.ensure(2 * sizeof(float) * (size_t)std::max<int64_t>(c->n, 1));
+        c->val2.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->nnz, 1));
         for (int p = 0; p < 2; ++p)
             for (int32_t c0 = 0; c0 < c->ld; c0 += c->slice_cols) {
                 sl.push_back(slice_desc(c, p, c0));
                 // a persistent grid's occupancy query, outside any capture
                 if (p == 0)
-                    prime_spmm(choose_variant(CLEORA_F32, std::min(c->slice_cols, c->ld - c0)),
+                    prime_spmm(choose_variant(c->dtype, std::min(c->slice_cols, c->ld - c0)),
                                c->persist, true);
             }
         c->slice_desc.ensure(sizeof(StepDesc) * sl.size());
@@ -881,8 +882,9 @@ void write_descs(cleora_ctx *c, hipStream_t s)
 StepDesc slice_desc(const cleora_ctx *c, int parity, int32_t c0)
 {
     StepDesc d = host_desc(c, parity);  // the row stride stays ld
-    d.Ein = static_cast<const float *>(d.Ein) + c0;
-    d.Eout = static_cast<float *>(d.Eout) + c0;
+    const size_t off = (size_t)c0 * (c->dtype == CLEORA_BF16 ? 2 : 4);
+    d.Ein = static_cast<const char *>(d.Ein) + off;
+    d.Eout = static_cast<char *>(d.Eout) + off;
     d.row_ss = c->slice_norms.as<float>();
     d.keep_rows = 1;
     return d;

@@ -122,6 +122,16 @@ int32_t padded_ld(int32_t dim, int dtype)
 // halves against 256, the SpMM is unchanged; 1024 slows the SpMM).
 constexpr int32_t DEFAULT_SPLIT = 512;
 
+// Column slices of iterations: requested width in columns (0: whole rows)
+// -> width in use.  A bfloat16 width is rounded up to whole 16-byte
+// vectors; a slice as wide as the row is whole rows.
+int32_t slice_width(int32_t req, int32_t dtype, int32_t ld)
+{
+    const int32_t epv = dtype == CLEORA_BF16 ? 8 : 4;
+    const int32_t w = (req + epv - 1) / epv * epv;
+    return w >= ld ? 0 : w;
+}
+
 void check_dim(int32_t dim, int32_t dtype)
 {
     if (dtype != CLEORA_F32 && dtype != CLEORA_BF16) throw Error(CLEORA_E_INVAL, "unknown dtype");
@@ -146,102 +156,77 @@ hipEvent_t take_event(cleora_ctx *c)
     return e;
 }
 
-// Where the timing events of queued launches go: the context's eager list
-// (events from its pool) or a graph being captured (fresh events that the
-// graph owns).  No lists: no timing.
-struct Timers {
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> *spmm = nullptr, *comb = nullptr;
-    bool fresh = false;
-};
-
-hipEvent_t timer_event(cleora_ctx *c, const Timers &t)
-{
-    if (!t.fresh) return take_event(c);
-    hipEvent_t e;
-    CLEORA_HIP(hipEventCreate(&e));
-    return e;
-}
-
-// One spmm (+ combine) launch of enqueue_steps, with timing events when
-// asked for.
+// One spmm (+ combine) launch of enqueue_steps, with timing events when on.
 void launch_step(cleora_ctx *c, const cleora::Variant &v, const StepDesc &d,
-                 const StepDesc *dev_desc, hipStream_t s, const Timers &t)
+                 const StepDesc *dev_desc, hipStream_t s)
 {
     hipEvent_t a = nullptr, b = nullptr;
-    if (t.spmm) {
-        a = timer_event(c, t);
-        b = timer_event(c, t);
-        t.spmm->emplace_back(a, b);
+    if (c->timing) {
+        a = take_event(c);
+        b = take_event(c);
         CLEORA_HIP(hipEventRecord(a, s));
     }
     cleora::launch_spmm(v, d, s);
-    if (t.spmm) CLEORA_HIP(hipEventRecord(b, s));
+    if (c->timing) {
+        CLEORA_HIP(hipEventRecord(b, s));
+        c->ev_spmm.emplace_back(a, b);
+    }
     if (c->n_long > 0) {
-        if (t.comb) {
-            a = timer_event(c, t);
-            b = timer_event(c, t);
-            t.comb->emplace_back(a, b);
+        if (c->timing) {
+            a = take_event(c);
+            b = take_event(c);
             CLEORA_HIP(hipEventRecord(a, s));
         }
         cleora::launch_combine(v, dev_desc, 1, c->n_long, s);
-        if (t.comb) CLEORA_HIP(hipEventRecord(b, s));
+        if (c->timing) {
+            CLEORA_HIP(hipEventRecord(b, s));
+            c->ev_comb.emplace_back(a, b);
+        }
     }
 }
 
-// k iterations as column slices (FP32): every slice stores its rows
-// unscaled and adds its squared norms; then 1/norm per row and one pass
-// that scales the rows, so T_t is complete after every iteration.
-// (Applying the factors inside the next iteration's gather instead, and
-// scaling only at the end, was slower: each entry then also reads its
-// neighbour's factor from an N-long vector.)
-void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s, const Timers &tm)
+// k iterations as column slices.  Each slice's SpMM gathers that
+// part of the neighbour rows (a narrower gather keeps more of the most-used
+// rows in cache), stores its rows unscaled and adds its share of each row's
+// squared norm; 1/norm per row follows.  The factors are not applied to
+// the rows: the next iteration reads M diag(1/norm) instead of M (one pass
+// over the stored values), so T_t = diag(1/norm) U_t is never written
+// between iterations.  At the end of the call T_k is written once, out of
+// place, into the other buffer; the unscaled rows and their factors stay
+// for the next call, which continues from them (deferred = true).
+void enqueue_sliced_steps(cleora_ctx *c, int32_t k, int cur, bool deferred, hipStream_t s)
 {
     const int64_t n = c->n;
     const int32_t B = c->slice_cols, S = (c->ld + B - 1) / B;
     float *ss = c->slice_norms.as<float>(), *inv = ss + n;
+    int in = deferred ? cur ^ 1 : cur;
     for (int32_t t = 0; t < k; ++t) {
+        const bool unscaled_in = t > 0 || deferred;
+        if (unscaled_in)
+            cleora::launch_scale_values(c->val.as<float>(), c->col.as<int32_t>(), inv, c->nnz,
+                                        c->val2.as<float>(), s);
         cleora::launch_fill_zero(ss, n, s);
         for (int32_t j = 0; j < S; ++j) {
             const int32_t c0 = j * B;
-            const cleora::Variant v = cleora::choose_variant(CLEORA_F32, std::min(B, c->ld - c0));
-            launch_step(c, v, cleora::slice_desc(c, cur, c0),
-                        c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s, tm);
+            const cleora::Variant v = cleora::choose_variant(c->dtype, std::min(B, c->ld - c0));
+            StepDesc d = cleora::slice_desc(c, in, c0);
+            if (unscaled_in) d.val = c->val2.as<float>();
+            launch_step(c, v, d, c->slice_desc.as<StepDesc>() + (size_t)in * S + j, s);
         }
         cleora::launch_inv_norm(ss, inv, n, s);
-        cleora::launch_scale_rows(c->E[cur ^ 1].as<float>(), n, c->ld, inv, s);
-        cur ^= 1;
+        in ^= 1;
     }
+    cleora::launch_scale_rows_to(c->dtype, c->E[in].p, c->E[in ^ 1].p, n, c->ld, inv, s);
 }
 
 // Queue k iterations starting from buffer parity `cur` (no state change).
-void enqueue_steps(cleora_ctx *c, int32_t k, int cur, hipStream_t s, const Timers &tm)
+void enqueue_steps(cleora_ctx *c, int32_t k, int cur, bool deferred, hipStream_t s)
 {
-    if (c->slice_cols > 0) return enqueue_sliced_steps(c, k, cur, s, tm);
+    if (c->slice_cols > 0) return enqueue_sliced_steps(c, k, cur, deferred, s);
     const cleora::Variant v = cleora::choose_variant(c->dtype, c->ld);
     for (int32_t t = 0; t < k; ++t) {
-        launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s, tm);
+        launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
         cur ^= 1;
-    }
-}
-
-// Add the durations of a graph's last replay to the context's totals.
-void read_graph_events(cleora_ctx *c, cleora::LoopGraph &L)
-{
-    if (!L.unread) return;
-    L.unread = false;
-    for (auto &p : L.ev_spmm) {
-        CLEORA_HIP(hipEventSynchronize(p.second));
-        float ms = 0;
-        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        c->t_spmm_ms += ms;
-        c->t_spmm_n++;
-    }
-    for (auto &p : L.ev_comb) {
-        CLEORA_HIP(hipEventSynchronize(p.second));
-        float ms = 0;
-        CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        c->t_comb_ms += ms;
-        c->t_comb_n++;
     }
 }
 
@@ -251,11 +236,6 @@ void free_loop(cleora::LoopGraph &L)
     if (L.done && L.launched) (void)hipEventSynchronize(L.done);
     if (L.exec) (void)hipGraphExecDestroy(L.exec);
     if (L.done) (void)hipEventDestroy(L.done);
-    for (auto *v : {&L.ev_spmm, &L.ev_comb})
-        for (auto &p : *v) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
-        }
     L = cleora::LoopGraph{};
 }
 
@@ -267,17 +247,18 @@ void drop_graphs(cleora_ctx *c)
 
 // Everything a captured k-iteration loop depends on: kernel arguments of
 // both parities (buffers, schedule sizes, layout, flags, grid choice), the
-// device descriptor tables, the slicing and timing.  Equal signatures mean
+// device descriptor tables and the slicing.  Equal signatures mean
 // the captured launches are exactly the ones enqueue_steps would queue now.
 std::vector<int64_t> loop_signature(const cleora_ctx *c, int32_t k, int cur)
 {
     std::vector<int64_t> g;
     auto P = [&](const void *p) { g.push_back((int64_t)reinterpret_cast<uintptr_t>(p)); };
-    g.insert(g.end(), {k, cur, c->timing ? 1 : 0, c->dtype, c->ld, c->slice_cols, c->n,
-                       c->n_long});
+    g.insert(g.end(), {k, cur, c->deferred ? 1 : 0, c->dtype, c->ld, c->slice_cols, c->n,
+                       c->nnz, c->n_long});
     P(c->desc.p);
     P(c->slice_desc.p);
     P(c->slice_norms.p);
+    P(c->val2.p);
     for (int p = 0; p < 2; ++p) {
         const StepDesc d = cleora::host_desc(c, p);
         P(d.rp);
@@ -301,19 +282,17 @@ std::vector<int64_t> loop_signature(const cleora_ctx *c, int32_t k, int cur)
 // exists.
 cleora::LoopGraph &loop_graph(cleora_ctx *c, int32_t k)
 {
-    cleora::LoopGraph &L = c->graphs[std::make_tuple(k, c->cur, c->timing)];
+    cleora::LoopGraph &L = c->graphs[std::make_tuple(k, c->cur, c->deferred)];
     std::vector<int64_t> sig = loop_signature(c, k, c->cur);
     if (L.exec && L.sig == sig) return L;
     free_loop(L);
     if (!c->cap_stream) CLEORA_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
-    Timers tm;
-    if (c->timing) tm = Timers{&L.ev_spmm, &L.ev_comb, true};
     try {
         CLEORA_HIP(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
         CLEORA_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         try {
-            enqueue_steps(c, k, c->cur, c->cap_stream, tm);
+            enqueue_steps(c, k, c->cur, c->deferred, c->cap_stream);
         } catch (...) {
             (void)hipStreamEndCapture(c->cap_stream, &g);
             if (g) (void)hipGraphDestroy(g);
@@ -332,27 +311,31 @@ cleora::LoopGraph &loop_graph(cleora_ctx *c, int32_t k)
     return L;
 }
 
-// k >= 2 iterations run as one captured graph (cached per k, starting
-// parity and timing): the 2k launches cost one graph launch.  With timing
-// on, the graph records events around its launches; they are read before
-// the next replay overwrites them, or by cleora_kernel_time.
+// k >= 2 iterations without timing run as one captured graph (cached per
+// k and starting parity, and reused while its launch parameters hold): the
+// 2k launches cost one graph launch.  With timing on, launches are eager,
+// each between two events (events recorded inside a graph carry no time).
 void run_steps(cleora_ctx *c, int32_t k, hipStream_t s)
 {
     if (k <= 0) return;
-    if (k >= 2) {
+    if (k >= 2 && !c->timing) {
         cleora::LoopGraph &L = loop_graph(c, k);
-        read_graph_events(c, L);
         CLEORA_HIP(hipGraphLaunch(L.exec, s));
         CLEORA_HIP(hipEventRecord(L.done, s));
         L.launched = true;
-        L.unread = c->timing;
         c->graph_launches++;
     } else {
-        Timers tm;
-        if (c->timing) tm = Timers{&c->ev_spmm, &c->ev_comb, false};
-        enqueue_steps(c, k, c->cur, s, tm);
+        enqueue_steps(c, k, c->cur, c->deferred, s);
     }
-    c->cur ^= (k & 1);
+    if (c->slice_cols > 0) {
+        // the last unscaled rows are in the buffer the k iterations ended
+        // in; T_k was written into the other one
+        const int in0 = c->deferred ? c->cur ^ 1 : c->cur;
+        c->cur = in0 ^ (k & 1) ^ 1;
+        c->deferred = true;
+    } else {
+        c->cur ^= (k & 1);
+    }
     c->iteration += k;
 }
 
@@ -374,7 +357,8 @@ void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
     c->dtype = dtype;
     c->ld = padded_ld(dim, dtype);
     c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
-    c->slice_cols = dtype == CLEORA_F32 ? c->slice_req : 0;
+    c->deferred = false;
+    c->slice_cols = slice_width(c->slice_req, dtype, c->ld);
     const size_t ebytes = (size_t)n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
@@ -460,7 +444,7 @@ std::vector<DevBuf *> ctx_buffers(cleora_ctx *c)
             &c->t_local,    &c->t_expand,   &c->t_edges,     &c->t_wts,      &c->t_cnt,
             &c->t_off,      &c->t_keys,     &c->t_tmp,       &c->t_head,     &c->t_pos,
             &c->t_esum,     &c->t_lists,    &c->t_scan,      &c->t_small,    &c->multi_desc,
-            &c->slice_desc, &c->slice_norms};
+            &c->slice_desc, &c->slice_norms, &c->val2};
 }
 
 int64_t ctx_device_bytes(cleora_ctx *c)
@@ -518,7 +502,10 @@ void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s)
     launch_spmm_multi(v, d, n, waves, c0->persist, s);
     if (blocks > 0) launch_combine(v, d, n, blocks, s);
     for (int32_t i = 0; i < n; ++i) {
+        // a whole-row step from the normalised rows (the other buffer, which
+        // held a sliced context's unscaled rows, now holds the result)
         ctxs[i]->cur ^= 1;
+        ctxs[i]->deferred = false;
         ctxs[i]->iteration++;
     }
     // the descriptor table is host memory read by the copy above
@@ -526,6 +513,53 @@ void step_contexts(cleora_ctx *const *ctxs, int32_t n, hipStream_t s)
 }
 
 void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+void check_rows_args(int64_t n_rows, int64_t n_cols, int64_t m, const int32_t *rows,
+                     const int32_t *cols, const void *T_in, int64_t ld_in, int32_t dim,
+                     int32_t dtype, const void *out, int64_t ld_out)
+{
+    if (!T_in || !out) throw Error(CLEORA_E_INVAL, "NULL argument");
+    check_graph_sizes(n_rows, m);
+    check_graph_sizes(n_cols, 0);
+    if (m > 0 && (!rows || !cols)) throw Error(CLEORA_E_INVAL, "rows/cols is NULL");
+    check_dim(dim, dtype);
+    if (ld_in != padded_ld(dim, dtype))
+        throw Error(CLEORA_E_INVAL, "ld_in must be dim rounded up to a multiple of 16 bytes");
+    if (ld_out < dim) throw Error(CLEORA_E_INVAL, "ld_out < dim");
+    if ((reinterpret_cast<uintptr_t>(T_in) & 15) != 0)
+        throw Error(CLEORA_E_INVAL, "T_in must be 16-byte aligned");
+}
+
+void propagate_rows_into(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t m,
+                         const int32_t *rows, const int32_t *cols, const float *w,
+                         const void *T_in, int32_t dim, int32_t dtype, void *out, int64_t ld_out,
+                         hipStream_t s)
+{
+    c->is_chunk = false;
+    build_graph(c, n_rows, n_cols, m, rows, cols, w, CLEORA_DIRECTED, s);
+    c->dim = dim;
+    c->dtype = dtype;
+    c->ld = padded_ld(dim, dtype);
+    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
+    const size_t ebytes = (size_t)n_rows * (size_t)c->ld * elem_size(dtype);
+    c->E[1].ensure(ebytes);
+    plan_schedule(c, s);
+    c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
+    StepDesc d = host_desc(c, 0);
+    d.Ein = T_in;
+    d.Eout = c->E[1].p;
+    c->desc.ensure(sizeof(StepDesc) * 2);
+    CLEORA_HIP(hipMemcpyAsync(c->desc.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    const Variant v = choose_variant(dtype, c->ld);
+    launch_spmm(v, d, s);
+    if (c->n_long > 0) launch_combine(v, c->desc.as<StepDesc>(), 1, c->n_long, s);
+    const size_t es = elem_size(dtype);
+    CLEORA_HIP(hipMemcpy2DAsync(out, (size_t)ld_out * es, c->E[1].p, (size_t)c->ld * es,
+                                (size_t)dim * es, (size_t)n_rows, hipMemcpyDefault, s));
+    // the descriptor above lives on this stack frame
+    CLEORA_HIP(hipStreamSynchronize(s));
+    c->has_emb = false;  // the scratch context holds no propagatable embedding
+}
 
 namespace {
 // Concatenated per-graph edges -> block-diagonal ids, in place: edge e of
@@ -756,7 +790,7 @@ int cleora_release_scratch(cleora_ctx *c)
         drop_graphs(c);  // captured iterations point at the buffers below
         DevBuf *emb[] = {&c->E[0],      &c->E[1],       &c->split_items, &c->bucket_row,
                          &c->long_rows, &c->chunk_base, &c->partial,     &c->desc,
-                         &c->blk_norms, &c->slice_desc, &c->slice_norms};
+                         &c->blk_norms, &c->slice_desc, &c->slice_norms, &c->val2};
         for (DevBuf *b : emb) b->release();
     }
     return CLEORA_OK;
@@ -803,6 +837,10 @@ int cleora_previous_embedding_ptr(cleora_ctx *c, const void **ptr, int64_t *ld)
     if (!c || !ptr) return fail(CLEORA_E_INVAL, "NULL argument");
     if (!c->has_emb || c->iteration < 1)
         return fail(CLEORA_E_STATE, "no previous iteration (propagate at least once)");
+    if (c->deferred)
+        return fail(CLEORA_E_STATE,
+                    "column-sliced iterations keep T_t's unscaled rows, not T_{t-1} "
+                    "(cleora_set_slices(ctx, 0) before cleora_init keeps whole rows)");
     *ptr = c->E[c->cur ^ 1].p;
     if (ld) *ld = c->ld;
     return CLEORA_OK;
@@ -816,42 +854,11 @@ int cleora_propagate_rows(cleora_ctx *c, int64_t n_rows, int64_t n_cols, int64_t
 {
     ABI_BEGIN
     cleora::TraceRange trace_range("cleora_propagate_rows");
-    if (!c || !T_in || !out) return fail(CLEORA_E_INVAL, "NULL argument");
-    check_graph_sizes(n_rows, m);
-    check_graph_sizes(n_cols, 0);
-    if (m > 0 && (!rows || !cols)) return fail(CLEORA_E_INVAL, "rows/cols is NULL");
-    check_dim(dim, dtype);
-    if (ld_in != padded_ld(dim, dtype))
-        return fail(CLEORA_E_INVAL, "ld_in must be dim rounded up to a multiple of 16 bytes");
-    if (ld_out < dim) return fail(CLEORA_E_INVAL, "ld_out < dim");
-    if ((reinterpret_cast<uintptr_t>(T_in) & 15) != 0)
-        return fail(CLEORA_E_INVAL, "T_in must be 16-byte aligned");
+    if (!c) return fail(CLEORA_E_INVAL, "NULL argument");
+    cleora::check_rows_args(n_rows, n_cols, m, rows, cols, T_in, ld_in, dim, dtype, out, ld_out);
     DeviceGuard g(c->device);
-    hipStream_t s = cleora::as_stream(stream);
-    c->is_chunk = false;
-    cleora::build_graph(c, n_rows, n_cols, m, rows, cols, w, CLEORA_DIRECTED, s);
-    c->dim = dim;
-    c->dtype = dtype;
-    c->ld = (int32_t)ld_in;
-    c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
-    const size_t ebytes = (size_t)n_rows * (size_t)c->ld * elem_size(dtype);
-    c->E[1].ensure(ebytes);
-    cleora::plan_schedule(c, s);
-    c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
-    StepDesc d = cleora::host_desc(c, 0);
-    d.Ein = T_in;
-    d.Eout = c->E[1].p;
-    c->desc.ensure(sizeof(StepDesc) * 2);
-    CLEORA_HIP(hipMemcpyAsync(c->desc.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
-    const cleora::Variant v = cleora::choose_variant(dtype, c->ld);
-    cleora::launch_spmm(v, d, s);
-    if (c->n_long > 0) cleora::launch_combine(v, c->desc.as<StepDesc>(), 1, c->n_long, s);
-    const size_t es = elem_size(dtype);
-    CLEORA_HIP(hipMemcpy2DAsync(out, (size_t)ld_out * es, c->E[1].p, (size_t)c->ld * es,
-                                (size_t)dim * es, (size_t)n_rows, hipMemcpyDefault, s));
-    // the descriptor above lives on this stack frame
-    CLEORA_HIP(hipStreamSynchronize(s));
-    c->has_emb = false;  // the scratch context holds no propagatable embedding
+    cleora::propagate_rows_into(c, n_rows, n_cols, m, rows, cols, w, T_in, dim, dtype, out,
+                                ld_out, cleora::as_stream(stream));
     return CLEORA_OK;
     ABI_END
 }
@@ -890,7 +897,8 @@ int cleora_info(cleora_ctx *c, int64_t *n, int64_t *nnz, int32_t *dim, int32_t *
 }
 
 int cleora_schedule_info(cleora_ctx *c, int32_t *chunk, int64_t *n_split, int64_t *n_long,
-                         int64_t *n_buckets, int32_t *pack, int32_t *persistent)
+                         int64_t *n_buckets, int32_t *pack, int32_t *persistent,
+                         int32_t *slice_cols)
 {
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
@@ -901,6 +909,7 @@ int cleora_schedule_info(cleora_ctx *c, int32_t *chunk, int64_t *n_split, int64_
     if (n_split) *n_split = c->n_split;
     if (n_long) *n_long = c->n_long;
     if (n_buckets) *n_buckets = c->n_buckets;
+    if (slice_cols) *slice_cols = c->slice_cols;
     return CLEORA_OK;
     ABI_END
 }
@@ -929,8 +938,8 @@ int cleora_set_slices(cleora_ctx *c, int32_t cols)
 {
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
-    if (cols < 0 || (cols > 0 && (cols % 4 != 0 || cols > CLEORA_MAX_DIM_F32)))
-        return fail(CLEORA_E_INVAL, "cols must be 0 or a multiple of 4 up to 4096");
+    if (cols < 0 || (cols > 0 && (cols % 4 != 0 || cols > CLEORA_MAX_DIM_BF16)))
+        return fail(CLEORA_E_INVAL, "cols must be 0 or a multiple of 4 up to 8192");
     c->slice_req = cols;
     return CLEORA_OK;
     ABI_END
@@ -1045,6 +1054,9 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
     }
     c->pack_req = 0;  // the cache entry now applies to this and later inits
     c->persist_req = -1;
+    // trial steps wrote the other buffer: a sliced context's unscaled rows
+    // are gone, so it continues from the normalised rows
+    c->deferred = false;
     cleora::plan_schedule(c, s);
     c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
     cleora::write_descs(c, s);
@@ -1070,30 +1082,26 @@ int cleora_kernel_time(cleora_ctx *c, double *spmm_ms, int64_t *spmm_n, double *
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
     DeviceGuard g(c->device);
+    double a = 0, b = 0;
     for (auto &p : c->ev_spmm) {
         CLEORA_HIP(hipEventSynchronize(p.second));
         float ms = 0;
         CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        c->t_spmm_ms += ms;
-        c->t_spmm_n++;
+        a += ms;
     }
     for (auto &p : c->ev_comb) {
         CLEORA_HIP(hipEventSynchronize(p.second));
         float ms = 0;
         CLEORA_HIP(hipEventElapsedTime(&ms, p.first, p.second));
-        c->t_comb_ms += ms;
-        c->t_comb_n++;
+        b += ms;
     }
+    if (spmm_ms) *spmm_ms = a;
+    if (spmm_n) *spmm_n = (int64_t)c->ev_spmm.size();
+    if (comb_ms) *comb_ms = b;
+    if (comb_n) *comb_n = (int64_t)c->ev_comb.size();
     c->ev_spmm.clear();
     c->ev_comb.clear();
     c->ev_next = 0;
-    for (auto &kv : c->graphs) read_graph_events(c, kv.second);
-    if (spmm_ms) *spmm_ms = c->t_spmm_ms;
-    if (spmm_n) *spmm_n = c->t_spmm_n;
-    if (comb_ms) *comb_ms = c->t_comb_ms;
-    if (comb_n) *comb_n = c->t_comb_n;
-    c->t_spmm_ms = c->t_comb_ms = 0;
-    c->t_spmm_n = c->t_comb_n = 0;
     return CLEORA_OK;
     ABI_END
 }

@@ -85,7 +85,7 @@ def test_more_error_paths_without_gpu(lib):
     assert lib.cleora_build_init(null, 10, 0, null, null, null, 0, 16, 0, 1, null) == _lib.E_INVAL
     assert lib.cleora_set_schedule(null, 0, -1) == _lib.E_INVAL
     assert lib.cleora_autotune(null, null, null, null, null) == _lib.E_INVAL
-    assert lib.cleora_schedule_info(null, null, null, null, null, null, null) == _lib.E_INVAL
+    assert lib.cleora_schedule_info(null, null, null, null, null, null, null, null) == _lib.E_INVAL
     assert lib.cleora_set_chunk(null, 0) == _lib.E_INVAL
     assert lib.cleora_embed_blocked(null, 16, 4, 0, 1, 2, null, 16, null) == _lib.E_INVAL
     assert lib.cleora_release_scratch(null) == _lib.E_INVAL
