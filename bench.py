@@ -182,7 +182,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out: str, command: str,
         f.write("\n")
 
 
-def served_main(args) -> dict:
+def served_main(args, trace=None, graphs=None) -> dict:
     """Served stream: Poisson arrivals of independent Chung-Lu requests
     (N log-uniform in [100, 200k], mean degree U(5, 30), d = 128, k = 4).
     1. capacity of the continuous-batching server (the library's native
@@ -197,10 +197,8 @@ def served_main(args) -> dict:
     from paper_2102_02302_amd.serve import Job, NativeServer, run_native
 
     dim, k = 128, 4
-    t0 = time.time()
-    trace = gen.served_trace(args.requests, 1.0)
-    graphs = gen.materialize(trace, workers=min(16, os.cpu_count() or 1))
-    print(f"[served] generated {len(graphs)} requests in {time.time() - t0:.1f}s", flush=True)
+    if trace is None:
+        trace, graphs = served_inputs(args.requests)
 
     def jobs(scale):
         return [Job(index=r.index, arrival_s=r.arrival_s * scale, n=g.n, m=g.m, seed=r.seed,
@@ -229,6 +227,17 @@ def served_main(args) -> dict:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _served_cpu_baseline(trace, graphs, dim, k)
     return out
+
+
+def served_inputs(n_requests: int):
+    """The served stream's requests and their graphs (drawn in worker
+    processes: call before the GPU is used)."""
+    import gen
+    t0 = time.time()
+    trace = gen.served_trace(n_requests, 1.0)
+    graphs = gen.materialize(trace, workers=min(16, os.cpu_count() or 1))
+    print(f"[served] generated {len(graphs)} requests in {time.time() - t0:.1f}s", flush=True)
+    return trace, graphs
 
 
 def _served_cpu_baseline(trace, graphs, dim: int, k: int, n_sample: int = 200) -> dict:
@@ -466,6 +475,9 @@ def parse():
     ap.add_argument("--blocked", type=int, default=0,
                     help="run the column-blocked form instead, this many columns per block")
     ap.add_argument("--requests", type=int, default=10_000)
+    ap.add_argument("--served-requests", type=int, default=2000,
+                    help="requests of the reduced served stream reported beside the default "
+                         "line (0: none)")
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--budget-gib", type=int, default=64)
@@ -562,6 +574,7 @@ def main():
     g = _cached_graph(args.graph_cache, args.workload, spec)
     gen_s = time.time() - t0
     print(f"[bench] generated {args.workload}: n={g.n} m={g.m} in {gen_s:.1f}s", flush=True)
+    served_in = served_inputs(args.served_requests) if args.served_requests > 0 else None
 
     dev = torch.device("cuda", 0)
     if args.calibrate_copy_gib > 0:
@@ -623,10 +636,34 @@ def main():
                       "propagate_only": o["propagate_only"], "phases_ms": o["phases_ms"],
                       "roofline": o["roofline"]}
     ctx.close()
-    del ctx
+    del ctx, src, dst, w
+    torch.cuda.empty_cache()
+    if served_in is not None:
+        out["served"] = _served_summary(args, *served_in)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(g, dim, k)
     print(json.dumps(out), flush=True)
+
+
+def _served_summary(args, trace, graphs) -> dict:
+    """The reduced served stream beside the default line: the native
+    server's saturated capacity, then p50/p99 latency and throughput at
+    0.7 x that capacity (continuous batching, BF16) against the same
+    arrivals served one at a time by the plain FP32 path."""
+    import copy
+    a = copy.copy(args)
+    a.requests, a.loads, a.rates, a.no_cpu_baseline = len(graphs), "", "", True
+    res = served_main(a, trace, graphs)
+    keys = ("p50_ms", "p99_ms", "req_per_s", "gedge_dims_per_s")
+    cb, base = res["continuous_batching"], res["one_at_a_time_f32"]
+    return {"requests": res["requests"], "dim": res["dim"], "k": res["k"],
+            "saturated_req_per_s": res["saturated_capacity"]["req_per_s"],
+            "load": res["load"], "offered_req_per_s": res["offered_req_per_s"],
+            "continuous_batching": {"dtype": cb["dtype"], **{x: cb[x] for x in keys}},
+            "one_at_a_time_f32": {x: base[x] for x in keys},
+            "stream": "Poisson arrivals, Chung-Lu requests (gamma 2.1), N log-uniform in "
+                      "[100, 200k], mean degree U(5, 30), seeded; a reduced trace of the "
+                      "10,000-request stream of --served"}
 
 
 def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, autotune, workload,
