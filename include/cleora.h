@@ -195,6 +195,28 @@ int cleora_propagate_rows(cleora_ctx *work, int64_t n_rows, int64_t n_cols, int6
                           const void *T_in, int64_t ld_in, int32_t dim, int32_t dtype, void *out,
                           int64_t ld_out, void *stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation):
+ * cleora_propagate_rows without a context.  Arguments, result and errors
+ * as cleora_propagate_rows, on HIP device `device`, within these limits:
+ * n_rows <= CLEORA_NOALLOC_MAX_ROWS, n_edges <= CLEORA_NOALLOC_MAX_EDGES
+ * and a row of T_in (ld_in elements) at most CLEORA_NOALLOC_MAX_ROW_BYTES;
+ * above them it returns E_INVAL and does nothing.  It allocates no device
+ * memory: its scratch (CSR build, schedule, partial sums, staging of the
+ * rows) is a static device array of about 80 MB that every GPU the library
+ * runs on holds until the process ends.  All calls on one GPU share that
+ * array, so calls that overlap on one GPU (from several threads or
+ * streams) race; each call synchronises `stream` before it returns, which
+ * also makes it unsuitable for stream capture.  Errors: as
+ * cleora_propagate_rows; E_DEVICE for a bad device. */
+#define CLEORA_NOALLOC_MAX_ROWS 8192
+#define CLEORA_NOALLOC_MAX_EDGES 524288
+#define CLEORA_NOALLOC_MAX_ROW_BYTES 4096
+int cleora_propagate_rows_noalloc(int device, int64_t n_rows, int64_t n_cols, int64_t n_edges,
+                                  const int32_t *rows, const int32_t *cols, const float *w,
+                                  const void *T_in, int64_t ld_in, int32_t dim, int32_t dtype,
+                                  void *out, int64_t ld_out, void *stream);
+
 /* Copy the built CSR into caller device buffers: row_ptr int64[N+1],
  * col int32[nnz], val float32[nnz] (M values), deg float64[N] (D).  Any of
  * them may be NULL.  Sizes come from cleora_info.  Errors: E_STATE. */

@@ -344,6 +344,29 @@ class Context:
         return {"graph_instantiations": a.value, "graph_launches": b.value}
 
 
+def propagate_rows_noalloc(n_rows: int, n_cols: int, rows, cols, T_in, dim: int, dtype="f32",
+                           w=None, out=None, device: int = 0, stream=None):
+    """``Context.propagate_rows`` without a context and without device
+    allocation inside the library (``cleora_propagate_rows_noalloc``; sizes
+    within the CLEORA_NOALLOC_* limits).  T_in: device tensor whose row
+    stride is dim rounded up to 16 bytes."""
+    torch = _torch()
+    code = _dtype_code(dtype)
+    tdt = torch.float32 if code == F32 else torch.bfloat16
+    r = _dev_i32(rows, device)
+    c = _dev_i32(cols, device)
+    wt = _dev_f32(w, device)
+    epv = 4 if code == F32 else 8
+    ld = (dim + epv - 1) // epv * epv
+    assert T_in.dtype == tdt and T_in.is_contiguous() and T_in.shape[1] == ld
+    if out is None:
+        out = torch.empty((n_rows, dim), dtype=tdt, device=T_in.device)
+    _lib.check(load().cleora_propagate_rows_noalloc(
+        int(device), int(n_rows), int(n_cols), int(r.numel()), _ptr(r), _ptr(c), _ptr(wt),
+        T_in.data_ptr(), ld, int(dim), code, out.data_ptr(), out.stride(0), _stream(stream)))
+    return out
+
+
 def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
           empty_keep: bool = False, chunk: int = 0, slices: int = 0):
     """Whole path for one graph: build M, initialise T_0, k iterations

@@ -21,13 +21,19 @@ MAX_DIM = {F32: 4096, BF16: 8192}
 _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",
           E_DEVICE: "E_DEVICE", E_INPUT: "E_INPUT"}
 
+# limits of cleora_propagate_rows_noalloc (cleora.h)
+NOALLOC_MAX_ROWS = 8192
+NOALLOC_MAX_EDGES = 524288
+NOALLOC_MAX_ROW_BYTES = 4096
+
 EXPORTS = [
     "cleora_create", "cleora_destroy", "cleora_footprint_bytes", "cleora_build_csr",
     "cleora_build_init",
     "cleora_init", "cleora_propagate", "cleora_embed_blocked", "cleora_release_scratch",
     "cleora_get_embedding",
     "cleora_embedding_ptr",
-    "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_get_csr", "cleora_info",
+    "cleora_previous_embedding_ptr", "cleora_propagate_rows", "cleora_propagate_rows_noalloc",
+    "cleora_get_csr", "cleora_info",
     "cleora_schedule_info", "cleora_sync", "cleora_set_chunk", "cleora_set_schedule",
     "cleora_set_slices",
     "cleora_set_timing",
@@ -100,6 +106,8 @@ def load() -> ctypes.CDLL:
                                                          ctypes.POINTER(i64)]),
         "cleora_propagate_rows": (ctypes.c_int, [p, i64, i64, i64, p, p, p, p, i64, i32, i32, p,
                                                  i64, p]),
+        "cleora_propagate_rows_noalloc": (ctypes.c_int, [ctypes.c_int, i64, i64, i64, p, p, p, p,
+                                                         i64, i32, i32, p, i64, p]),
         "cleora_get_csr": (ctypes.c_int, [p, p, p, p, p, p]),
         "cleora_info": (ctypes.c_int, [p, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                        ctypes.POINTER(i32), ctypes.POINTER(i32),

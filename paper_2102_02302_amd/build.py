@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libcleora.so")
 OBJDIR = os.path.join(PKG, "_build")
 SOURCES = ["scan.hip", "build_csr.hip", "propagate.hip", "blocked.hip", "chunked.hip",
-           "expand.hip", "runtime.hip", "server.hip"]
+           "expand.hip", "runtime.hip", "server.hip", "noalloc.hip"]
 ARCH = os.environ.get("CLEORA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -112,3 +112,25 @@ def test_more_error_paths_without_gpu(lib):
     assert lib.cleora_server_stats(null, null, null, null, null, null, null) == _lib.E_INVAL
     assert lib.cleora_server_now(null) == 0.0
     lib.cleora_server_destroy(null)
+
+
+def test_noalloc_limits_without_gpu(lib):
+    """The no-allocation entry point refuses sizes above its limits (and
+    bad arguments) before any device work; the limits of the binding are
+    the header's."""
+    from paper_2102_02302_amd import _lib
+    text = open(HEADER).read()
+    for name in ("MAX_ROWS", "MAX_EDGES", "MAX_ROW_BYTES"):
+        m = re.search(rf"#define CLEORA_NOALLOC_{name} (\d+)", text)
+        assert m and int(m.group(1)) == getattr(_lib, f"NOALLOC_{name}"), name
+    f = lib.cleora_propagate_rows_noalloc
+    T, out, ids = 1 << 12, 1 << 13, 1 << 14  # aligned stand-ins, never dereferenced
+    R, M = _lib.NOALLOC_MAX_ROWS, _lib.NOALLOC_MAX_EDGES
+    assert f(0, R + 1, 10, 5, ids, ids, None, T, 16, 16, 0, out, 16, None) == _lib.E_INVAL
+    assert b"limits" in lib.cleora_last_error()
+    assert f(0, R, 10, M + 1, ids, ids, None, T, 16, 16, 0, out, 16, None) == _lib.E_INVAL
+    # 1028 float32 columns: a 4112-byte row
+    assert f(0, 10, 10, 5, ids, ids, None, T, 1028, 1028, 0, out, 1028, None) == _lib.E_INVAL
+    assert f(0, 10, 10, 5, ids, ids, None, None, 16, 16, 0, out, 16, None) == _lib.E_INVAL
+    assert f(0, 10, 10, 5, ids, ids, None, T, 20, 16, 0, out, 16, None) == _lib.E_INVAL  # ld_in
+    assert f(0, 10, 10, 5, None, ids, None, T, 16, 16, 0, out, 16, None) == _lib.E_INVAL
