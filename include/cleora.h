@@ -396,7 +396,11 @@ typedef struct {
 } cleora_graph;
 
 /* Embed n_graphs independent graphs as one block-diagonal graph: one CSR
- * build, one T_0 initialisation and k iterations over all of them at once.
+ * build, one T_0 initialisation and k iterations over all of them at once
+ * (Algorithm 1 per graph: a block-diagonal M propagates each block on its
+ * own).  Besides unrelated graphs, this embeds the separate sparse matrix
+ * the paper builds for every pair of entity columns of a relation
+ * (Sections 4.2-4.3) in one call.
  * out[g] is a device float32/bf16 (per dtype) buffer of graphs[g].n_nodes x
  * dim elements, row stride dim.  The context's graph and embedding are
  * replaced by the block-diagonal ones.  Errors: as build/init/propagate;
