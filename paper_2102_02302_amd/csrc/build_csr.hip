@@ -104,10 +104,23 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     for (int i = t; i < (RS_THREADS / WAVE) * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int lane = t & 63;
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
+        // lanes with the same digit (often all of them, in the high digits
+        // of row ids) are counted by one LDS add of their number
         const int64_t idx = base + i * RS_THREADS + t;
-        if (idx < n) atomicAdd(&h[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t mk = __ballot(bit);
+            peers &= bit ? mk : ~mk;
+        }
+        if (valid && (peers & ((1ull << lane) - 1ull)) == 0)
+            atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     uint32_t s = 0;
@@ -223,55 +236,128 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     }
 }
 
-// head[i] = 1 for the first entry of each run of equal keys among the
-// n_valid sorted valid entries (0 beyond).
-__global__ void k_mark_heads(int64_t total, const unsigned long long *__restrict__ n_valid,
-                             const uint64_t *__restrict__ keys, uint8_t *__restrict__ head)
-{
-    const int64_t nv = (int64_t)*n_valid;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x)
-        head[i] = (i < nv && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
-}
+// Merging repeated pairs of the sorted keys (entries [0, total), invalid
+// keys last).  Entry i starts a merged entry (a run of equal keys) when it
+// is valid and differs from entry i - 1.  Block b covers indices
+// [b * RS_TILE, (b + 1) * RS_TILE) of [0, total], index total standing for
+// the end; wave w of the block a contiguous quarter of that, in rounds of 64.
+// A wave loads its keys once; entry i - 1 (and i + 1) come from the
+// neighbouring lane or round, and from memory only at the chunk's edges.
+struct MergeChunk {
+    uint64_t key[RS_ITEMS], prev[RS_ITEMS], hb[RS_ITEMS];
+};
 
-// One merged entry per run: key, column and e_ab (count or float64 sum of
-// the run's weights in input order).
-__global__ void k_compact(int64_t total, const unsigned long long *__restrict__ n_valid,
-                          const uint64_t *__restrict__ keys, const float *__restrict__ wts,
-                          const uint8_t *__restrict__ head, const int64_t *__restrict__ pos,
-                          uint64_t cmask, uint64_t *__restrict__ ukeys,
-                          int32_t *__restrict__ col_u, double *__restrict__ e_u)
+__device__ __forceinline__ void load_chunk(const uint64_t *__restrict__ keys, int64_t wbase,
+                                           int64_t total, uint64_t invalid_key, int lane,
+                                           MergeChunk &c)
 {
-    const int64_t nv = (int64_t)*n_valid;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (!head[i]) continue;
-        const int64_t u = pos[i];
-        ukeys[u] = keys[i];
-        col_u[u] = (int32_t)(keys[i] & cmask);
-        double s = wts ? (double)wts[i] : 1.0;
-        for (int64_t j = i + 1; j < nv && !head[j]; ++j) s += wts ? (double)wts[j] : 1.0;
-        e_u[u] = s;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = wbase + i * WAVE + lane;
+        c.key[i] = idx < total ? keys[idx] : 0;
     }
-    (void)total;
+    const uint64_t edge = wbase > 0 && wbase <= total ? keys[wbase - 1] : 0;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = wbase + i * WAVE + lane;
+        const uint64_t up = __shfl_up(c.key[i], 1, WAVE);
+        const uint64_t carry = i == 0 ? edge : __shfl(c.key[i > 0 ? i - 1 : 0], WAVE - 1, WAVE);
+        c.prev[i] = lane == 0 ? carry : up;
+        c.hb[i] = __ballot(idx < total && c.key[i] < invalid_key &&
+                           (idx == 0 || c.prev[i] != c.key[i]));
+    }
 }
 
-// rp[a] = first merged entry whose row is >= a.
-__global__ void k_rowptr_search(int64_t n, const int64_t *__restrict__ nnz_p,
-                                const uint64_t *__restrict__ ukeys, int cb,
-                                int64_t *__restrict__ rp)
+// hcount[b] = merged entries starting in block b.
+__global__ __launch_bounds__(RS_THREADS) void k_merge_count(const uint64_t *__restrict__ keys,
+                                                            int64_t total, uint64_t invalid_key,
+                                                            int64_t *__restrict__ hcount)
 {
-    const int64_t nnz = *nnz_p;
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a <= n;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t target = (uint64_t)a << cb;
-        int64_t lo = 0, hi = nnz;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (ukeys[mid] >= target) hi = mid;
-            else lo = mid + 1;
+    constexpr int NW = RS_THREADS / WAVE, CHUNK = RS_TILE / NW;
+    __shared__ uint32_t wsum[NW];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * CHUNK;
+    MergeChunk c;
+    load_chunk(keys, wbase, total, invalid_key, lane, c);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
+    if (lane == 0) wsum[w] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int64_t sum = 0;
+        for (int q = 0; q < NW; ++q) sum += wsum[q];
+        hcount[blockIdx.x] = sum;
+    }
+}
+
+// One merged entry per run, at hoff[b] + (runs before it in the block):
+// column and e_ab (count, or float64 sum of the run's weights in input
+// order).  Row pointers come from the same pass: where the row changes
+// between index i - 1 and i (the end and invalid keys count as row n),
+// rows (row(i - 1), row(i)] start at the number of merged entries before i.
+__global__ __launch_bounds__(RS_THREADS) void k_merge(
+    const uint64_t *__restrict__ keys, const float *__restrict__ wts, int64_t total,
+    uint64_t invalid_key, int cb, int64_t n, const int64_t *__restrict__ hoff,
+    int32_t *__restrict__ col_u, double *__restrict__ e_u, int64_t *__restrict__ rp)
+{
+    constexpr int NW = RS_THREADS / WAVE, CHUNK = RS_TILE / NW;
+    __shared__ uint32_t wsum[NW];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * CHUNK;
+    const uint64_t cmask = ((uint64_t)1 << cb) - 1;
+    MergeChunk c;
+    load_chunk(keys, wbase, total, invalid_key, lane, c);
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
+    if (lane == 0) wsum[w] = cnt;
+    __syncthreads();
+    int64_t u0 = hoff[blockIdx.x];
+    for (int q = 0; q < w; ++q) u0 += wsum[q];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    // entry after the chunk (for the last lane of the last round)
+    const int64_t after = wbase + CHUNK;
+    const uint64_t edge_next = after < total ? keys[after] : 0;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = wbase + i * WAVE + lane;
+        const int64_t u = u0 + __popcll(c.hb[i] & lt);  // merged entries before idx
+        u0 += __popcll(c.hb[i]);
+        const uint64_t k = c.key[i];
+        const uint64_t down = __shfl_down(k, 1, WAVE);
+        const uint64_t carry =
+            i + 1 < RS_ITEMS ? __shfl(c.key[i + 1 < RS_ITEMS ? i + 1 : i], 0, WAVE) : edge_next;
+        const uint64_t next = lane == WAVE - 1 ? carry : down;
+        if ((c.hb[i] >> lane) & 1ull) {
+            col_u[u] = (int32_t)(k & cmask);
+            double sum = wts ? (double)wts[idx] : 1.0;
+            if (idx + 1 < total && next == k) {  // a repeated pair: add up its run
+                for (int64_t j = idx + 1; j < total && keys[j] == k; ++j)
+                    sum += wts ? (double)wts[j] : 1.0;
+            }
+            e_u[u] = sum;
         }
-        rp[a] = lo;
+        // rows starting at idx (indices past the end start none)
+        int64_t r_lo = 0, r_hi = -1;
+        if (idx <= total) {
+            const uint64_t pk = c.prev[i];
+            const int64_t row = idx < total && k < invalid_key ? (int64_t)(k >> cb) : n;
+            const int64_t prow = idx == 0 ? -1 : pk < invalid_key ? (int64_t)(pk >> cb) : n;
+            r_lo = prow + 1;
+            r_hi = row;
+        }
+        if (r_hi - r_lo < WAVE) {
+            for (int64_t r = r_lo; r <= r_hi; ++r) rp[r] = u;
+        }
+        // a long run of empty rows: the whole wave writes it
+        uint64_t big = __ballot(r_hi - r_lo >= WAVE);
+        while (big) {
+            const int l = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const int64_t lo = __shfl(r_lo, l), hi = __shfl(r_hi, l), ul = __shfl(u, l);
+            for (int64_t r = lo + lane; r <= hi; r += WAVE) rp[r] = ul;
+        }
     }
 }
 
@@ -334,18 +420,32 @@ __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *_
         }
         return;
     }
-    for (int q = 0; q < nr; ++q) {
+    // the first 64 entries of all four rows are loaded before any is
+    // reduced (four independent loads in flight, not one after another)
+    int64_t lo[4], hi[4];
+    double first[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        lo[q] = q < nr ? rp[r0 + q] : 0;
+        hi[q] = q < nr ? rp[r0 + q + 1] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        first[q] = lo[q] + lane < hi[q] && hi[q] - lo[q] <= LONG_ROW ? e_u[lo[q] + lane] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q >= nr) break;
         const int64_t row = r0 + q;
-        const int64_t lo = rp[row], hi = rp[row + 1];
-        if (hi - lo > LONG_ROW) {
+        if (hi[q] - lo[q] > LONG_ROW) {
             if (lane == 0) long_list[atomicAdd(long_count, 1)] = (int32_t)row;
             continue;
         }
-        double s = 0.0;
-        for (int64_t j = lo + lane; j < hi; j += 64) s += e_u[j];
+        double s = first[q];
+        for (int64_t j = lo[q] + 64 + lane; j < hi[q]; j += 64) s += e_u[j];
         s = wave_sum(s);
         if (lane == 0) deg[row] = s;
-        for (int64_t j = lo + lane; j < hi; j += 64) val[j] = (float)(e_u[j] / s);
+        if (lo[q] + lane < hi[q]) val[lo[q] + lane] = (float)(first[q] / s);
+        for (int64_t j = lo[q] + 64 + lane; j < hi[q]; j += 64) val[j] = (float)(e_u[j] / s);
     }
 }
 
@@ -465,14 +565,12 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     const int cb = bits_for(n_cols), rb = bits_for(n + 1);
     const int key_bits = rb + cb;
     const uint64_t invalid_key = (uint64_t)n << cb;
-    const uint64_t cmask = ((uint64_t)1 << cb) - 1;
     const int64_t nblk = ceil_div(tot1, RS_TILE);
 
     c->t_small.ensure(sizeof(int64_t) * 8);
     c->t_keys.ensure(sizeof(uint64_t) * (size_t)tot1);
     c->t_tmp.ensure(sizeof(uint64_t) * (size_t)tot1);
     c->t_esum.ensure(sizeof(double) * (size_t)tot1);
-    c->t_head.ensure((size_t)tot1);
     // digit counts of a radix pass, later the long-row list and its segment counts
     c->t_cnt.ensure(sizeof(int32_t) * std::max(256 * (size_t)nblk, 2 * (size_t)n));
     const int64_t scan_max = std::max<int64_t>(std::max<int64_t>(tot1 + 1, 256 * nblk + 1), n + 1);
@@ -493,7 +591,6 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     float *wa = w ? c->t_wts.as<float>() : nullptr, *wb = w ? wa + tot1 : nullptr;
     int32_t *count = c->t_cnt.as<int32_t>();
     int64_t *pos = c->t_pos.as<int64_t>(), *ws = c->t_scan.as<int64_t>();
-    uint8_t *head = c->t_head.as<uint8_t>();
 
     CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
     if (m > 0) {
@@ -518,26 +615,24 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
             std::swap(wa, wb);
         }
     }
-    if (total > 0) {
-        k_count_valid<<<1, 1, 0, s>>>(total, keys, invalid_key, n_valid);
-        CLEORA_LAUNCH_CHECK();
-    }
-    // merge repeated pairs
-    const unsigned gt = grid_for(tot1, 256, 65536);
-    k_mark_heads<<<gt, 256, 0, s>>>(tot1, n_valid, keys, head);
+    // merge repeated pairs; row pointers
+    const int64_t nblk_m = ceil_div(total + 1, RS_TILE);  // indices [0, total]
+    int64_t *hcount = pos, *hoff = pos + nblk_m;           // nblk_m + (nblk_m + 1) entries
+    k_merge_count<<<(unsigned)nblk_m, RS_THREADS, 0, s>>>(keys, total, invalid_key, hcount);
     CLEORA_LAUNCH_CHECK();
-    exclusive_scan(head, tot1, pos, ws, s);
+    exclusive_scan(hcount, nblk_m, hoff, ws, s);
     if (occ) {
+        if (total > 0) {
+            k_count_valid<<<1, 1, 0, s>>>(total, keys, invalid_key, n_valid);
+            CLEORA_LAUNCH_CHECK();
+        }
         k_row_counts<<<grid_for(n, 256, 65536), 256, 0, s>>>(n, n_valid, keys, cb, occ);
         CLEORA_LAUNCH_CHECK();
     }
-    uint64_t *ukeys = tmpk;  // the other key buffer is free now
     double *esum = c->t_esum.as<double>();
-    k_compact<<<gt, 256, 0, s>>>(tot1, n_valid, keys, wa, head, pos, cmask, ukeys,
-                                 c->col.as<int32_t>(), esum);
-    CLEORA_LAUNCH_CHECK();
-    k_rowptr_search<<<grid_for(n + 1, 256, 65536), 256, 0, s>>>(n, pos + tot1, ukeys, cb,
-                                                                c->rp.as<int64_t>());
+    k_merge<<<(unsigned)nblk_m, RS_THREADS, 0, s>>>(keys, wa, total, invalid_key, cb, n, hoff,
+                                                    c->col.as<int32_t>(), esum,
+                                                    c->rp.as<int64_t>());
     CLEORA_LAUNCH_CHECK();
     // deg(a) and M values
     int32_t *long_list = count;  // the digit counts are no longer needed

@@ -29,15 +29,16 @@ def jobs_for(trace, graphs, time_scale):
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_served_results_equal_solo(cl, dtype):
-    """Poisson arrivals about every 0.1 ms, groups of at most two: requests
-    join while others step, and every result equals the request embedded
-    alone, bit for bit, and is within the stated tolerance of the FP64
-    oracle."""
+    """Poisson arrivals about every 20 us (well inside one request's build
+    and steps, so requests are always in flight together), groups of at
+    most two: requests join while others step, and every result equals the
+    request embedded alone, bit for bit, and is within the stated tolerance
+    of the FP64 oracle."""
     from paper_2102_02302_amd.serve import latency_stats, run_native
     trace = gen.served_trace(24, 1.0, n_lo=100, n_hi=20_000)
     graphs = gen.materialize(trace)
     dim, k = 64, 4
-    jobs = jobs_for(trace, graphs, 0.0001)
+    jobs = jobs_for(trace, graphs, 0.00002)
     done = run_native(jobs, dim, dtype, k, slots=6, budget_bytes=1 << 30, builders=2,
                       keep_results=True, max_group=2)
     assert len(done) == len(jobs)
