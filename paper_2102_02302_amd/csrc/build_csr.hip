@@ -105,13 +105,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const int lane = t & 63;
+    // all of the tile's loads are issued before any digit is counted
+    uint64_t key[RS_ITEMS];
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * RS_THREADS + t;
+        key[i] = idx < n ? keys[idx] : 0;
+    }
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
         // lanes with the same digit (often all of them, in the high digits
         // of row ids) are counted by one LDS add of their number
-        const int64_t idx = base + i * RS_THREADS + t;
-        const bool valid = idx < n;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+        const bool valid = base + i * RS_THREADS + t < n;
+        const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -145,12 +151,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
     static_assert(RS_THREADS == 256, "one thread per digit");
     __shared__ uint64_t sk[RS_TILE];
     __shared__ float sp[PAYLOAD ? RS_TILE : 1];
-    __shared__ uint32_t wc[NW][256];  // per-wave digit counts, then per-wave digit starts
+    // per-wave digit counts, then per-wave digit starts, then (as int64)
+    // each digit's output position minus its start in the tile
+    __shared__ __align__(16) uint32_t wc[NW][256];
     __shared__ uint32_t total[256];
     __shared__ uint32_t dstart[256];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const int64_t wbase = base + (int64_t)w * CHUNK;
+    // where this tile's keys of digit t go (loaded now, used at the end)
+    const int64_t goff = offs[(int64_t)t * nblk + blockIdx.x];
     uint64_t key[RS_ITEMS];
     float pay[PAYLOAD ? RS_ITEMS : 1];
 #pragma unroll
@@ -226,11 +236,13 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
         if constexpr (PAYLOAD) sp[lp] = pay[i];
     }
     __syncthreads();
+    int64_t *gbase = reinterpret_cast<int64_t *>(&wc[0][0]);  // wc is free now
+    gbase[t] = goff - (int64_t)dstart[t];
+    __syncthreads();
     const int64_t cnt = min((int64_t)RS_TILE, n - base);
     for (int j = t; j < cnt; j += RS_THREADS) {
         const uint64_t k = sk[j];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
-        const int64_t g = offs[(int64_t)d * nblk + blockIdx.x] + (j - dstart[d]);
+        const int64_t g = gbase[(uint32_t)(k >> shift) & 255u] + j;
         kout[g] = k;
         if constexpr (PAYLOAD) pout[g] = sp[j];
     }

@@ -57,26 +57,32 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x)
     return z ^ (z >> 31);
 }
 
-// U(-1,1) entry of T_0: 24 random bits k, value k * 2^-23 - 1 (exact).
-__device__ __forceinline__ float uniform_entry(uint64_t seed, int64_t i, int32_t d, int32_t j)
+// U(-1,1) entry of T_0 for the counter c = i * d + j: 24 random bits k,
+// value k * 2^-23 - 1 (exact).
+__device__ __forceinline__ float uniform_entry(uint64_t seed, uint64_t c)
 {
-    const uint64_t x = splitmix64(seed ^ splitmix64((uint64_t)i * (uint64_t)d + (uint64_t)j));
+    const uint64_t x = splitmix64(seed ^ splitmix64(c));
     return (float)(uint32_t)(x >> 40) * 0x1p-23f - 1.0f;
 }
 
+// T_0 rows (or columns [j0, j0 + dim) of rows of width dfull).  Thread t
+// owns 16-byte vector v0 = t % vt of rows t / vt, t / vt + rps, ... (vt
+// threads per row, rps rows per sweep; vectors v0 + vt, ... too when a row
+// has more vectors than the grid has threads): the division happens once per
+// thread, and each row's counter base i * dfull + j0 once per row.
 template <typename T>
 __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
                        const int64_t *__restrict__ row0, const uint64_t *__restrict__ seeds,
                        int n_graphs, uint64_t seed0, const int32_t *__restrict__ ids,
-                       int32_t dfull, int32_t j0)
+                       int32_t dfull, int32_t j0, int32_t vt, int32_t rps)
 {
     constexpr int EPV = 16 / sizeof(T);
-    const int64_t vpr = ld / EPV;
-    const int64_t total = n * vpr;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = idx / vpr;
-        const int32_t v = (int32_t)(idx - row * vpr);
+    const int32_t vpr = ld / EPV;
+    const int32_t tid = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int32_t r0 = tid / vt;
+    if (r0 >= rps) return;
+    const int32_t v0 = tid - r0 * vt;
+    for (int64_t row = r0; row < n; row += rps) {
         int64_t local = row;
         uint64_t seed = seed0;
         if (row0) {
@@ -90,24 +96,28 @@ __global__ void k_init(T *__restrict__ E, int64_t n, int32_t dim, int32_t ld,
             seed = seeds[lo];
         }
         if (ids) local = ids[row];
-        float x[EPV];
+        const uint64_t cbase = (uint64_t)local * (uint64_t)dfull + (uint64_t)j0;
+        uint4 *out_row = reinterpret_cast<uint4 *>(E + row * (int64_t)ld);
+        for (int32_t v = v0; v < vpr; v += vt) {
+            float x[EPV];
 #pragma unroll
-        for (int e = 0; e < EPV; ++e) {
-            const int32_t j = v * EPV + e;
-            x[e] = j < dim ? uniform_entry(seed, local, dfull, j0 + j) : 0.0f;
-        }
-        uint4 out;
-        if constexpr (sizeof(T) == 4) {
-            out = make_uint4(__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]),
-                             __float_as_uint(x[3]));
-        } else {
-            uint32_t p[4];
+            for (int e = 0; e < EPV; ++e) {
+                const int32_t j = v * EPV + e;
+                x[e] = j < dim ? uniform_entry(seed, cbase + (uint64_t)j) : 0.0f;
+            }
+            uint4 out;
+            if constexpr (sizeof(T) == 4) {
+                out = make_uint4(__float_as_uint(x[0]), __float_as_uint(x[1]),
+                                 __float_as_uint(x[2]), __float_as_uint(x[3]));
+            } else {
+                uint32_t p[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                p[q] = f32_to_bf16_rne(x[2 * q]) | (f32_to_bf16_rne(x[2 * q + 1]) << 16);
-            out = make_uint4(p[0], p[1], p[2], p[3]);
+                for (int q = 0; q < 4; ++q)
+                    p[q] = f32_to_bf16_rne(x[2 * q]) | (f32_to_bf16_rne(x[2 * q + 1]) << 16);
+                out = make_uint4(p[0], p[1], p[2], p[3]);
+            }
+            out_row[v] = out;
         }
-        reinterpret_cast<uint4 *>(E)[idx] = out;
     }
 }
 
@@ -763,14 +773,18 @@ void launch_init(int dtype, void *E, int64_t n, int32_t dim, int32_t ld, const i
 {
     if (dfull <= 0) dfull = dim;
     const int epv = dtype == CLEORA_BF16 ? 8 : 4;
-    const int64_t total = n * (ld / epv);
+    const int64_t vpr = ld / epv, total = n * vpr;
     const unsigned g = grid_for(total, 256, max_blocks > 0 ? max_blocks : 1 << 16);
+    // vt threads per row, rps rows per sweep (vt * rps <= the grid's threads)
+    const int64_t threads = (int64_t)g * 256;
+    const int32_t vt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(vpr, threads));
+    const int32_t rps = (int32_t)std::max<int64_t>(1, threads / vt);
     if (dtype == CLEORA_BF16)
         k_init<uint16_t><<<g, 256, 0, s>>>(reinterpret_cast<uint16_t *>(E), n, dim, ld, row0,
-                                           seeds, n_graphs, seed0, ids, dfull, j0);
+                                           seeds, n_graphs, seed0, ids, dfull, j0, vt, rps);
     else
         k_init<float><<<g, 256, 0, s>>>(reinterpret_cast<float *>(E), n, dim, ld, row0, seeds,
-                                        n_graphs, seed0, ids, dfull, j0);
+                                        n_graphs, seed0, ids, dfull, j0, vt, rps);
     CLEORA_LAUNCH_CHECK();
 }
 
