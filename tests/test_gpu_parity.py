@@ -141,6 +141,34 @@ def test_csr_long_rows_weighted(cl):
         assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001 + 1e-30)
 
 
+def test_csr_runs_of_empty_rows(cl):
+    # edges only among a few node ranges: long runs of empty rows at the
+    # start, between the ranges and at the end (row pointers of a run of
+    # 64 or more empty rows are written by a whole wave), loops, repeated
+    # weighted pairs; undirected weighted and directed unweighted
+    rng = np.random.default_rng(12)
+    n = 20_000
+    parts = []
+    ranges = [(1000, 1100, 3000), (5000, 5010, 200), (5075, 5076, 5), (12_000, 12_400, 4000)]
+    for lo, hi, m in ranges:  # (5075, 5076): loops only
+        parts.append((rng.integers(lo, hi, m), rng.integers(lo, hi, m)))
+    src = np.concatenate([a for a, _ in parts]).astype(np.int32)
+    dst = np.concatenate([b for _, b in parts]).astype(np.int32)
+    w = rng.lognormal(0, 1, src.size).astype(np.float32)
+    cases = [gen.Graph(n, src, dst, w, False, "ranges"),
+             gen.Graph(n, src, dst, None, True, "ranges-directed")]
+    for g in cases:
+        adj = oracle.build_graph(g)
+        mval, deg = oracle.transition(adj)
+        with cl.Context(0) as ctx:
+            ctx.build_graph(g)
+            csr = {k: v.cpu().numpy() for k, v in ctx.csr().items()}
+        assert np.array_equal(csr["row_ptr"], adj.row_ptr), g.name
+        assert np.array_equal(csr["col"], adj.col), g.name
+        assert np.allclose(csr["deg"], deg, rtol=1e-14, atol=0)
+        assert np.all(np.abs(csr["val"] - mval) <= mval * 2.0**-24 * 1.0001 + 1e-30)
+
+
 # ------------------------------------------------------ propagation
 
 @pytest.mark.parametrize("gi", range(6))
