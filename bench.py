@@ -461,8 +461,11 @@ def parse():
     ap.add_argument("--dim", type=int, default=None,
                     help="override the workload's d (e.g. one GPU's share of the columns)")
     ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--slices", type=int, default=0,
-                    help="run each iteration as column slices this wide (0: whole rows)")
+    ap.add_argument("--slices", default="auto",
+                    help="column slices of each iteration: 'auto' (the autotuner times whole "
+                         "rows against 512-byte slices on this process's buffers and keeps "
+                         "the faster; whole rows with --no-autotune), 0 whole rows, or a "
+                         "width in columns")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's schedule autotuner (run once per graph "
@@ -592,8 +595,10 @@ def main():
     ctx = cl.Context(0)
     if args.chunk:
         ctx.set_chunk(args.chunk)
-    if args.slices:
-        ctx.set_slices(args.slices)
+    if args.slices == "auto":
+        ctx.set_slices("auto")
+    elif int(args.slices):
+        ctx.set_slices(int(args.slices))
 
     main_run = _measure(ctx, g, src, dst, w, dim, k, dtype, args.steps, args.warmup,
                         not args.no_autotune, args.workload,
@@ -615,7 +620,7 @@ def main():
         "config": {"workload": args.workload, "desc": spec["desc"], "n_nodes": n,
                    "n_edges": g.m, "nnz": nnz, "dim": dim, "k": k,
                    "step": "build CSR + FP64 row sums + init T_0 + k iterations",
-                   "column_slices": main_run["n_slices"],
+                   "column_slices": main_run["n_slices"], "slice_mode": str(args.slices),
                    "parallelism": "single GPU"},
         "propagate_only": main_run["propagate_only"],
         "phases_ms": main_run["phases_ms"],
@@ -633,6 +638,7 @@ def main():
         out[other] = {"value": o["value"], "unit": "GEdge-dims/s", "steps": o_steps,
                       "ms_per_step": o["ms_per_step"],
                       "speedup_vs_" + dtype: round(o["value"] / main_run["value"], 3),
+                      "column_slices": o["n_slices"],
                       "propagate_only": o["propagate_only"], "phases_ms": o["phases_ms"],
                       "roofline": o["roofline"]}
     ctx.close()
@@ -755,7 +761,7 @@ def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, autotune, worklo
     compulsory = (n_slices * nnz * 8 + n * dim * esz + (n - split_rows) * dim * esz) / n_slices
     achieved = spmm_bytes / (spmm_ms * 1e-3) / 1e9
     # the counter summaries are of the workload's own d
-    traffic = _traffic(workload, dtype) if traffic_ok else None
+    traffic = _traffic(workload, dtype, sched["slice_cols"]) if traffic_ok else None
     # one iteration on the production path: the captured loop's time over k
     iter_ms = loop_ms / max(k, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -792,8 +798,12 @@ def _measure(ctx, g, src, dst, w, dim, k, dtype, steps, warmup, autotune, worklo
             "roofline": roofline}
 
 
-def _traffic(workload: str, dtype: str):
-    path = PMC_SUMMARY.format(workload=workload, dtype=dtype)
+def _traffic(workload: str, dtype: str, slice_cols: int = 0):
+    """Measured HBM bytes per SpMM launch from the committed counter summary
+    of this workload, storage type and slicing (per slice launch when
+    sliced), or None if there is none for the current kernel source."""
+    tag = dtype if not slice_cols else f"{dtype}_slices{slice_cols}"
+    path = PMC_SUMMARY.format(workload=workload, dtype=tag)
     if not os.path.exists(path):
         return None
     with open(path) as f:

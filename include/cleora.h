@@ -268,8 +268,19 @@ int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
  * returns E_STATE.  cleora_step_multi steps whole rows from the normalised
  * T_t, and cleora_autotune's trial steps discard the unscaled rows: the
  * context continues from the normalised T_t.  cleora_propagate_rows uses
- * whole rows.  Errors: E_INVAL (cols < 0, not a multiple of 4, or above
- * 8192). */
+ * whole rows.
+ * cols = CLEORA_SLICES_AUTO: whole rows until cleora_autotune has measured,
+ * on this context's embedding and in this process, one whole-row iteration
+ * against one iteration in slices of 512 bytes (128 float32 or 256
+ * bfloat16 columns) plus the final out-of-place scaling spread over the
+ * iterations of the context's last cleora_propagate call (4 if none), and
+ * kept slices only if they are at least 1% faster (the choice is not
+ * cached across processes: on large embeddings the time of both forms
+ * depends on where the two buffers landed in physical memory); a later
+ * cleora_init with another dim or dtype returns to whole rows until the
+ * next cleora_autotune.  cleora_schedule_info reports the width in use.
+ * Errors: E_INVAL (cols < -1, not a multiple of 4, or above 8192). */
+#define CLEORA_SLICES_AUTO (-1)
 int cleora_set_slices(cleora_ctx *ctx, int32_t cols);
 
 /* Fix the propagation schedule instead of the autotuned or default one
@@ -293,9 +304,11 @@ int cleora_set_schedule(cleora_ctx *ctx, int32_t pack, int32_t persistent);
  * any context, uses the cached choice.  With the environment variable
  * CLEORA_TUNE_CACHE naming a file, choices are also read from that file
  * (once per process, also by inits that never call the autotuner) and
- * each new choice is appended to it, one text line per graph shape.  Outputs (may be NULL): the chosen
- * packing size, 1 if the persistent grid won (else 0), and the time per
- * step in ms.  Errors: E_STATE (no embedding), E_DEVICE. */
+ * each new choice is appended to it, one text line per graph shape.  With
+ * cleora_set_slices(ctx, CLEORA_SLICES_AUTO) it then also chooses between
+ * whole rows and column slices (see there).  Outputs (may be NULL): the
+ * chosen packing size, 1 if the persistent grid won (else 0), and the time
+ * per step in ms (whole rows).  Errors: E_STATE (no embedding), E_DEVICE. */
 int cleora_autotune(cleora_ctx *ctx, int32_t *pack, int32_t *persistent, float *step_ms,
                     void *stream);
 

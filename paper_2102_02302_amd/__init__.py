@@ -144,11 +144,14 @@ class Context:
     def set_chunk(self, chunk: int) -> None:
         _lib.check(self._lib.cleora_set_chunk(self._h, int(chunk)))
 
-    def set_slices(self, cols: int) -> None:
+    def set_slices(self, cols) -> None:
         """Column slices of the next init's iterations: 0 whole rows (the
         default), else ``cols`` wide (results differ from whole rows in
-        rounding only)."""
-        _lib.check(self._lib.cleora_set_slices(self._h, int(cols)))
+        rounding only); ``"auto"``: whole rows until ``autotune`` has timed
+        both on this embedding and kept the faster (``schedule()["slice_cols"]``
+        reports the width in use)."""
+        code = _lib.SLICES_AUTO if cols == "auto" else int(cols)
+        _lib.check(self._lib.cleora_set_slices(self._h, code))
 
     def set_schedule(self, pack: int = 0, persistent: int = -1) -> None:
         """Fix the packing size (0: automatic) and SpMM grid (-1: automatic,
@@ -368,15 +371,18 @@ def propagate_rows_noalloc(n_rows: int, n_cols: int, rows, cols, T_in, dim: int,
 
 
 def embed(g, dim: int, k: int, seed: int = 0, dtype="f32", device: int = 0,
-          empty_keep: bool = False, chunk: int = 0, slices: int = 0):
+          empty_keep: bool = False, chunk: int = 0, slices=0):
     """Whole path for one graph: build M, initialise T_0, k iterations
-    (``slices``: the column slices of the iterations, 0 whole rows)."""
+    (``slices``: the column slices of the iterations, 0 whole rows; with
+    ``"auto"`` the autotuner runs and chooses)."""
     with Context(device) as ctx:
         if chunk:
             ctx.set_chunk(chunk)
         if slices:
             ctx.set_slices(slices)
         ctx.build_graph_init(g, dim, dtype, seed, empty_keep=empty_keep)
+        if slices == "auto":
+            ctx.autotune()
         ctx.propagate(k)
         return ctx.embedding()
 

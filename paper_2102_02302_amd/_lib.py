@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("CLEORA_LIB", os.path.join(_HERE, "libcleora.so"))
 OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_INPUT = range(6)
 F32, BF16 = 0, 1
 DIRECTED, EMPTY_KEEP = 1, 2
+SLICES_AUTO = -1  # cleora_set_slices: the autotuner chooses whole rows or slices
 MAX_DIM = {F32: 4096, BF16: 8192}
 
 _CODES = {E_INVAL: "E_INVAL", E_STATE: "E_STATE", E_NOMEM: "E_NOMEM",

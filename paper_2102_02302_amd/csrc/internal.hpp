@@ -184,6 +184,10 @@ struct cleora_ctx {
     // normalised T_t and E[cur ^ 1] the unscaled rows it was scaled from,
     // with their factors in slice_norms (the next iteration reads those).
     int32_t slice_req = 0, slice_cols = 0;
+    // CLEORA_SLICES_AUTO: the autotuner's choice (0: whole rows) and the
+    // embedding layout it was measured on
+    int32_t slice_auto = 0, slice_auto_dim = 0, slice_auto_dtype = -1;
+    int32_t last_k = 0;  // iterations of the last cleora_propagate call
     bool deferred = false;
     cleora::DevBuf slice_desc, slice_norms, val2;
 

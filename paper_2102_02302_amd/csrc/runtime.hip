@@ -132,6 +132,14 @@ int32_t slice_width(int32_t req, int32_t dtype, int32_t ld)
     return w >= ld ? 0 : w;
 }
 
+// The width asked for: the set one, or under CLEORA_SLICES_AUTO the
+// autotuner's choice for this layout (whole rows until it has measured).
+int32_t slice_request(const cleora_ctx *c, int32_t dim, int32_t dtype)
+{
+    if (c->slice_req != CLEORA_SLICES_AUTO) return c->slice_req;
+    return c->slice_auto_dim == dim && c->slice_auto_dtype == dtype ? c->slice_auto : 0;
+}
+
 void check_dim(int32_t dim, int32_t dtype)
 {
     if (dtype != CLEORA_F32 && dtype != CLEORA_BF16) throw Error(CLEORA_E_INVAL, "unknown dtype");
@@ -228,6 +236,93 @@ void enqueue_steps(cleora_ctx *c, int32_t k, int cur, bool deferred, hipStream_t
         launch_step(c, v, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
         cur ^= 1;
     }
+}
+
+// CLEORA_SLICES_AUTO: time one whole-row iteration (the schedule in use)
+// against one steady-state iteration in 512-byte slices (values of
+// M diag(1/norm), the slices' SpMM and combines, 1/norm) plus the final
+// out-of-place scaling spread over the iterations of the context's last
+// propagate call (4 if none yet), on this embedding; slices are kept only
+// if at least 1% faster.  The trials read E[cur] and write only the other
+// buffer and the slices' scratch (their values are not used), so the
+// embedding stays as it was.
+void choose_slices(cleora_ctx *c, hipStream_t s)
+{
+    const int32_t W = slice_width(512 / (int32_t)elem_size(c->dtype), c->dtype, c->ld);
+    int32_t chosen = 0;
+    if (W > 0 && c->n > 0) {
+        hipEvent_t a, b;
+        CLEORA_HIP(hipEventCreate(&a));
+        CLEORA_HIP(hipEventCreate(&b));
+        auto timed = [&](int reps, const std::function<void()> &f) {
+            f();  // warm-up
+            CLEORA_HIP(hipEventRecord(a, s));
+            for (int r = 0; r < reps; ++r) f();
+            CLEORA_HIP(hipEventRecord(b, s));
+            CLEORA_HIP(hipEventSynchronize(b));
+            float ms = 0;
+            CLEORA_HIP(hipEventElapsedTime(&ms, a, b));
+            return ms / (float)reps;
+        };
+        const bool timing = c->timing;
+        c->timing = false;
+        try {
+            const int cur = c->cur;
+            c->slice_cols = 0;
+            cleora::plan_schedule(c, s);
+            c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
+                              (size_t)c->ld);
+            cleora::write_descs(c, s);
+            const cleora::Variant vw = cleora::choose_variant(c->dtype, c->ld);
+            const float whole = timed(2, [&]() {
+                launch_step(c, vw, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
+            });
+            c->slice_cols = W;
+            cleora::write_descs(c, s);
+            const int32_t S = (c->ld + W - 1) / W;
+            float *ss = c->slice_norms.as<float>(), *inv = ss + c->n;
+            cleora::launch_fill_zero(inv, c->n, s);
+            const float sliced = timed(2, [&]() {
+                cleora::launch_scale_values(c->val.as<float>(), c->col.as<int32_t>(), inv, c->nnz,
+                                            c->val2.as<float>(), s);
+                cleora::launch_fill_zero(ss, c->n, s);
+                for (int32_t j = 0; j < S; ++j) {
+                    const int32_t c0 = j * W;
+                    const cleora::Variant v =
+                        cleora::choose_variant(c->dtype, std::min(W, c->ld - c0));
+                    StepDesc d = cleora::slice_desc(c, cur, c0);
+                    d.val = c->val2.as<float>();
+                    launch_step(c, v, d, c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s);
+                }
+                cleora::launch_inv_norm(ss, inv, c->n, s);
+            });
+            const float final_scale = timed(1, [&]() {
+                cleora::launch_scale_rows_to(c->dtype, c->E[cur].p, c->E[cur ^ 1].p, c->n, c->ld,
+                                             inv, s);
+            });
+            const int32_t per_call = c->last_k > 0 ? c->last_k : 4;
+            if (sliced + final_scale / (float)per_call < 0.99f * whole) chosen = W;
+            if (std::getenv("CLEORA_TUNE_VERBOSE"))
+                std::fprintf(stderr,
+                             "[cleora autotune] n=%lld d=%d: whole rows %.4f ms, %d-column "
+                             "slices %.4f + final scaling %.4f / %d ms -> %s\n",
+                             (long long)c->n, c->dim, whole, W, sliced, final_scale, per_call,
+                             chosen ? "slices" : "whole rows");
+        } catch (...) {
+            c->timing = timing;
+            c->slice_cols = 0;
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            throw;
+        }
+        c->timing = timing;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    c->slice_auto = chosen;
+    c->slice_auto_dim = c->dim;
+    c->slice_auto_dtype = c->dtype;
+    c->slice_cols = chosen;
 }
 
 // Release a captured loop after its last replay has finished.
@@ -358,7 +453,7 @@ void alloc_embedding(cleora_ctx *c, int64_t n, int32_t dim, int32_t dtype)
     c->ld = padded_ld(dim, dtype);
     c->chunk = c->chunk_req > 0 ? c->chunk_req : DEFAULT_SPLIT;
     c->deferred = false;
-    c->slice_cols = slice_width(c->slice_req, dtype, c->ld);
+    c->slice_cols = slice_width(slice_request(c, dim, dtype), dtype, c->ld);
     const size_t ebytes = (size_t)n * (size_t)c->ld * elem_size(dtype);
     c->E[0].ensure(ebytes);
     c->E[1].ensure(ebytes);
@@ -745,6 +840,7 @@ int cleora_propagate(cleora_ctx *c, int32_t k, void *stream)
     if (!c->has_emb) return fail(CLEORA_E_STATE, "no embedding: call cleora_init first");
     DeviceGuard g(c->device);
     run_steps(c, k, cleora::as_stream(stream));
+    if (k > 0) c->last_k = k;
     return CLEORA_OK;
     ABI_END
 }
@@ -938,8 +1034,9 @@ int cleora_set_slices(cleora_ctx *c, int32_t cols)
 {
     ABI_BEGIN
     if (!c) return fail(CLEORA_E_INVAL, "ctx is NULL");
-    if (cols < 0 || (cols > 0 && (cols % 4 != 0 || cols > CLEORA_MAX_DIM_BF16)))
-        return fail(CLEORA_E_INVAL, "cols must be 0 or a multiple of 4 up to 8192");
+    if (cols < CLEORA_SLICES_AUTO || (cols > 0 && (cols % 4 != 0 || cols > CLEORA_MAX_DIM_BF16)))
+        return fail(CLEORA_E_INVAL,
+                    "cols must be 0, CLEORA_SLICES_AUTO or a multiple of 4 up to 8192");
     c->slice_req = cols;
     return CLEORA_OK;
     ABI_END
@@ -1057,6 +1154,21 @@ int cleora_autotune(cleora_ctx *c, int32_t *pack, int32_t *persistent, float *st
     // trial steps wrote the other buffer: a sliced context's unscaled rows
     // are gone, so it continues from the normalised rows
     c->deferred = false;
+    if (c->slice_req == CLEORA_SLICES_AUTO) {
+        try {
+            choose_slices(c, s);
+        } catch (...) {
+            try {
+                cleora::plan_schedule(c, s);
+                c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
+                                  (size_t)c->ld);
+                cleora::write_descs(c, s);
+            } catch (...) {
+                c->has_emb = false;
+            }
+            throw;
+        }
+    }
     cleora::plan_schedule(c, s);
     c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) * (size_t)c->ld);
     cleora::write_descs(c, s);

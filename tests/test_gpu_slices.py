@@ -201,12 +201,14 @@ def test_bf16_slices(cl, gi, dim, cols):
 def test_set_slices_rejects_bad_values(cl):
     from paper_2102_02302_amd import _lib
     with cl.Context(0) as ctx:
-        for cols in (-1, 6, 8196):
+        for cols in (-2, 6, 8196):
             with pytest.raises(cl.CleoraError) as e:
                 ctx.set_slices(cols)
             assert e.value.code == _lib.E_INVAL
         ctx.set_slices(0)
         ctx.set_slices(8192)
+        ctx.set_slices("auto")
+        ctx.set_slices(_lib.SLICES_AUTO)
 
 
 def test_embed_with_slices(cl):
@@ -224,3 +226,33 @@ def test_release_scratch_keeps_a_sliced_embedding(cl):
         ctx.release_scratch()  # the slice buffers belong to the embedding
         ctx.propagate(1)
         assert np.array_equal(ctx.embedding().cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("dtype,dim,width", [("f32", 1024, 128), ("bf16", 1024, 256),
+                                             ("f32", 100, 0)])
+def test_auto_slices(cl, dtype, dim, width):
+    # whole rows until the autotuner has timed both; then the faster of
+    # whole rows and 512-byte slices (none when the row is not wider), with
+    # results bit-identical to setting that width by hand; another dim
+    # returns to whole rows until the next autotune; the embedding the
+    # autotuner ran on is unchanged
+    g = graphs()[0]
+    with cl.Context(0) as ctx:
+        ctx.set_slices("auto")
+        ctx.build_graph(g).init(dim, dtype, 4)
+        assert ctx.schedule()["slice_cols"] == 0
+        before = ctx.embedding().float().cpu().numpy()
+        ctx.autotune()
+        chosen = ctx.schedule()["slice_cols"]
+        assert chosen in ((0, width) if width else (0,)), chosen
+        assert np.array_equal(ctx.embedding().float().cpu().numpy(), before)
+        ctx.propagate(1).propagate(3)
+        got = ctx.embedding().float().cpu().numpy()
+        ctx.init(dim, dtype, 4)  # same layout: the choice stays
+        assert ctx.schedule()["slice_cols"] == chosen
+        ctx.init(dim - 4, dtype, 4)
+        assert ctx.schedule()["slice_cols"] == 0
+    print(f"{dtype} d={dim}: autotuner chose slice width {chosen}")
+    # the same 1 + 3 iterations from T_0 with the chosen width set by hand
+    want = run(cl, g, dim, 4, 4, chosen, dtype=dtype, steps=[1, 3])
+    assert np.array_equal(got, want)

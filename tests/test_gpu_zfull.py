@@ -10,8 +10,9 @@
   sampled rows, which the oracle computes one by one from the seed, the
   same properties after all k iterations, and BF16 against FP32.
 * ``chunglu10m`` (the benchmarked workload) after all k = 5 iterations,
-  in the launch configuration ``bench.py`` times (autotuned schedule,
-  captured k-iteration graph), against the full FP64 oracle on a seeded
+  in the launch configurations ``bench.py`` times (autotuned schedule,
+  captured k-iteration graph; whole rows and the 512-byte column slices
+  the autotuner may choose instead), against the full FP64 oracle on a seeded
   100k-row sample and on the 1000 highest-degree rows (the
   oracle's two 82 GB buffers need about 185 GB of host memory and a few
   minutes of 16 cores; skipped, saying so, only where the host has less
@@ -266,23 +267,30 @@ def test_chunglu10m_all_iterations_vs_oracle(cl, chunglu10m, capsys):
         rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 3)
         idx = torch.as_tensor(rows, device="cuda")
         got = {}
-        with cl.Context(0) as ctx:
-            for dt in ("f32", "bf16"):
+        # whole rows and 512-byte column slices: the two forms the
+        # autotuner chooses between for the benchmark
+        for dt, width in (("f32", 0), ("f32", 128), ("bf16", 0), ("bf16", 256)):
+            with cl.Context(0) as ctx:
+                ctx.set_slices(width)
                 ctx.build_graph(g).init(dim, dt, 11)
-                print(f"chunglu10m {dt} autotune: {ctx.autotune()}", flush=True)
+                print(f"chunglu10m {dt} slices {width} autotune: {ctx.autotune()}", flush=True)
+                assert ctx.schedule()["slice_cols"] == width
                 ctx.propagate(k)
-                got[dt] = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
-                torch.cuda.empty_cache()
-        print(f"GPU FP32 and BF16 done ({time.time() - t0:.0f}s)", flush=True)
+                got[dt, width] = ctx.embedding("f32")[idx].cpu().numpy().astype(np.float64)
+            torch.cuda.empty_cache()
+        print(f"GPU FP32 and BF16, whole rows and slices, done ({time.time() - t0:.0f}s)",
+              flush=True)
 
         want = oracle_rows_after_k(g, dim, k, 11, rows, t0, "chunglu10m")
 
         in_sample = np.isin(rows, sample)
         in_top = np.isin(rows, top)
         for name, m in (("random 100k", in_sample), ("top-1000 degree", in_top)):
-            e32 = float(np.abs(got["f32"][m] - want[m]).max())
-            e16, c16 = rowwise_report(got["bf16"][m], want[m])
-            print(f"chunglu10m k={k} vs FP64 oracle, {name} rows: FP32 max-abs {e32:.3e}; "
-                  f"BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
-            assert e32 <= F32_TOL
-            assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
+            for (w32, w16) in ((0, 0), (128, 256)):
+                e32 = float(np.abs(got["f32", w32][m] - want[m]).max())
+                e16, c16 = rowwise_report(got["bf16", w16][m], want[m])
+                form = "whole rows" if not w32 else "slices"
+                print(f"chunglu10m k={k} vs FP64 oracle, {name} rows, {form}: FP32 max-abs "
+                      f"{e32:.3e}; BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
+                assert e32 <= F32_TOL
+                assert e16 <= BF16_MAXABS and c16 >= BF16_MINCOS
