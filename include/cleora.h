@@ -271,10 +271,11 @@ int cleora_set_chunk(cleora_ctx *ctx, int32_t chunk);
  * whole rows.
  * cols = CLEORA_SLICES_AUTO: whole rows until cleora_autotune has measured,
  * on this context's embedding and in this process, one whole-row iteration
- * against one iteration in slices of 512 bytes (128 float32 or 256
- * bfloat16 columns) plus the final out-of-place scaling spread over the
- * iterations of the context's last cleora_propagate call (4 if none), and
- * kept slices only if they are at least 1% faster (the choice is not
+ * against one iteration in slices of 1 KiB and of 512 bytes (256 and 128
+ * float32, or 512 and 256 bfloat16 columns), each plus the final
+ * out-of-place scaling spread over the iterations of the context's last
+ * cleora_propagate call (4 if none), and kept the fastest slicing only if
+ * it is at least 1% faster than whole rows (the choice is not
  * cached across processes: on large embeddings the time of both forms
  * depends on where the two buffers landed in physical memory); a later
  * cleora_init with another dim or dtype returns to whole rows until the

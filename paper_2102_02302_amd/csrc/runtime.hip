@@ -239,18 +239,23 @@ void enqueue_steps(cleora_ctx *c, int32_t k, int cur, bool deferred, hipStream_t
 }
 
 // CLEORA_SLICES_AUTO: time one whole-row iteration (the schedule in use)
-// against one steady-state iteration in 512-byte slices (values of
-// M diag(1/norm), the slices' SpMM and combines, 1/norm) plus the final
-// out-of-place scaling spread over the iterations of the context's last
-// propagate call (4 if none yet), on this embedding; slices are kept only
-// if at least 1% faster.  The trials read E[cur] and write only the other
-// buffer and the slices' scratch (their values are not used), so the
-// embedding stays as it was.
+// against one steady-state iteration in slices of 1 KiB and of 512 bytes
+// (values of M diag(1/norm), the slices' SpMM and combines, 1/norm), each
+// plus the final out-of-place scaling spread over the iterations of the
+// context's last propagate call (4 if none yet), on this embedding; the
+// fastest slicing is kept only if at least 1% faster than whole rows.
+// The trials read E[cur] and write only the other buffer and the slices'
+// scratch (their values are not used), so the embedding stays as it was.
 void choose_slices(cleora_ctx *c, hipStream_t s)
 {
-    const int32_t W = slice_width(512 / (int32_t)elem_size(c->dtype), c->dtype, c->ld);
+    const int32_t esz = (int32_t)elem_size(c->dtype);
     int32_t chosen = 0;
-    if (W > 0 && c->n > 0) {
+    std::vector<int32_t> widths;
+    for (int32_t bytes : {1024, 512}) {
+        const int32_t W = slice_width(bytes / esz, c->dtype, c->ld);
+        if (W > 0) widths.push_back(W);
+    }
+    if (!widths.empty() && c->n > 0) {
         hipEvent_t a, b;
         CLEORA_HIP(hipEventCreate(&a));
         CLEORA_HIP(hipEventCreate(&b));
@@ -268,6 +273,7 @@ void choose_slices(cleora_ctx *c, hipStream_t s)
         c->timing = false;
         try {
             const int cur = c->cur;
+            const int32_t per_call = c->last_k > 0 ? c->last_k : 4;
             c->slice_cols = 0;
             cleora::plan_schedule(c, s);
             c->partial.ensure(sizeof(float) * (size_t)std::max<int64_t>(c->n_split, 1) *
@@ -277,37 +283,46 @@ void choose_slices(cleora_ctx *c, hipStream_t s)
             const float whole = timed(2, [&]() {
                 launch_step(c, vw, cleora::host_desc(c, cur), c->desc.as<StepDesc>() + cur, s);
             });
-            c->slice_cols = W;
-            cleora::write_descs(c, s);
-            const int32_t S = (c->ld + W - 1) / W;
-            float *ss = c->slice_norms.as<float>(), *inv = ss + c->n;
-            cleora::launch_fill_zero(inv, c->n, s);
-            const float sliced = timed(2, [&]() {
-                cleora::launch_scale_values(c->val.as<float>(), c->col.as<int32_t>(), inv, c->nnz,
-                                            c->val2.as<float>(), s);
-                cleora::launch_fill_zero(ss, c->n, s);
-                for (int32_t j = 0; j < S; ++j) {
-                    const int32_t c0 = j * W;
-                    const cleora::Variant v =
-                        cleora::choose_variant(c->dtype, std::min(W, c->ld - c0));
-                    StepDesc d = cleora::slice_desc(c, cur, c0);
-                    d.val = c->val2.as<float>();
-                    launch_step(c, v, d, c->slice_desc.as<StepDesc>() + (size_t)cur * S + j, s);
+            float best = 0.99f * whole;
+            for (int32_t W : widths) {
+                c->slice_cols = W;
+                cleora::write_descs(c, s);
+                const int32_t S = (c->ld + W - 1) / W;
+                float *ss = c->slice_norms.as<float>(), *inv = ss + c->n;
+                cleora::launch_fill_zero(inv, c->n, s);
+                const float sliced = timed(2, [&]() {
+                    cleora::launch_scale_values(c->val.as<float>(), c->col.as<int32_t>(), inv,
+                                                c->nnz, c->val2.as<float>(), s);
+                    cleora::launch_fill_zero(ss, c->n, s);
+                    for (int32_t j = 0; j < S; ++j) {
+                        const int32_t c0 = j * W;
+                        const cleora::Variant v =
+                            cleora::choose_variant(c->dtype, std::min(W, c->ld - c0));
+                        StepDesc d = cleora::slice_desc(c, cur, c0);
+                        d.val = c->val2.as<float>();
+                        launch_step(c, v, d, c->slice_desc.as<StepDesc>() + (size_t)cur * S + j,
+                                    s);
+                    }
+                    cleora::launch_inv_norm(ss, inv, c->n, s);
+                });
+                const float final_scale = timed(1, [&]() {
+                    cleora::launch_scale_rows_to(c->dtype, c->E[cur].p, c->E[cur ^ 1].p, c->n,
+                                                 c->ld, inv, s);
+                });
+                const float per_it = sliced + final_scale / (float)per_call;
+                if (per_it < best) {
+                    best = per_it;
+                    chosen = W;
                 }
-                cleora::launch_inv_norm(ss, inv, c->n, s);
-            });
-            const float final_scale = timed(1, [&]() {
-                cleora::launch_scale_rows_to(c->dtype, c->E[cur].p, c->E[cur ^ 1].p, c->n, c->ld,
-                                             inv, s);
-            });
-            const int32_t per_call = c->last_k > 0 ? c->last_k : 4;
-            if (sliced + final_scale / (float)per_call < 0.99f * whole) chosen = W;
+                if (std::getenv("CLEORA_TUNE_VERBOSE"))
+                    std::fprintf(stderr,
+                                 "[cleora autotune] n=%lld d=%d: whole rows %.4f ms, %d-column "
+                                 "slices %.4f + final scaling %.4f / %d ms\n",
+                                 (long long)c->n, c->dim, whole, W, sliced, final_scale, per_call);
+            }
             if (std::getenv("CLEORA_TUNE_VERBOSE"))
-                std::fprintf(stderr,
-                             "[cleora autotune] n=%lld d=%d: whole rows %.4f ms, %d-column "
-                             "slices %.4f + final scaling %.4f / %d ms -> %s\n",
-                             (long long)c->n, c->dim, whole, W, sliced, final_scale, per_call,
-                             chosen ? "slices" : "whole rows");
+                std::fprintf(stderr, "[cleora autotune] n=%lld d=%d: slice width %d kept\n",
+                             (long long)c->n, c->dim, chosen);
         } catch (...) {
             c->timing = timing;
             c->slice_cols = 0;

@@ -228,11 +228,12 @@ def test_release_scratch_keeps_a_sliced_embedding(cl):
         assert np.array_equal(ctx.embedding().cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("dtype,dim,width", [("f32", 1024, 128), ("bf16", 1024, 256),
-                                             ("f32", 100, 0)])
-def test_auto_slices(cl, dtype, dim, width):
-    # whole rows until the autotuner has timed both; then the faster of
-    # whole rows and 512-byte slices (none when the row is not wider), with
+@pytest.mark.parametrize("dtype,dim,widths", [("f32", 1024, (128, 256)), ("bf16", 1024, (256, 512)),
+                                              ("f32", 200, (128,)), ("f32", 100, ())])
+def test_auto_slices(cl, dtype, dim, widths):
+    # whole rows until the autotuner has timed both; then the fastest of
+    # whole rows and 1 KiB or 512-byte slices (only those narrower than the
+    # row), with
     # results bit-identical to setting that width by hand; another dim
     # returns to whole rows until the next autotune; the embedding the
     # autotuner ran on is unchanged
@@ -244,7 +245,7 @@ def test_auto_slices(cl, dtype, dim, width):
         before = ctx.embedding().float().cpu().numpy()
         ctx.autotune()
         chosen = ctx.schedule()["slice_cols"]
-        assert chosen in ((0, width) if width else (0,)), chosen
+        assert chosen in (0,) + widths, chosen
         assert np.array_equal(ctx.embedding().float().cpu().numpy(), before)
         ctx.propagate(1).propagate(3)
         got = ctx.embedding().float().cpu().numpy()

@@ -11,8 +11,9 @@
   same properties after all k iterations, and BF16 against FP32.
 * ``chunglu10m`` (the benchmarked workload) after all k = 5 iterations,
   in the launch configurations ``bench.py`` times (autotuned schedule,
-  captured k-iteration graph; whole rows and the 512-byte column slices
-  the autotuner may choose instead), against the full FP64 oracle on a seeded
+  captured k-iteration graph; whole rows and the 1 KiB and 512-byte
+  column slices the autotuner may choose instead), against the full FP64
+  oracle on a seeded
   100k-row sample and on the 1000 highest-degree rows (the
   oracle's two 82 GB buffers need about 185 GB of host memory and a few
   minutes of 16 cores; skipped, saying so, only where the host has less
@@ -267,9 +268,10 @@ def test_chunglu10m_all_iterations_vs_oracle(cl, chunglu10m, capsys):
         rows, sample, top, deg = sample_and_hubs(g, 100_000, 1000, 3)
         idx = torch.as_tensor(rows, device="cuda")
         got = {}
-        # whole rows and 512-byte column slices: the two forms the
+        # whole rows, 1 KiB and 512-byte column slices: the forms the
         # autotuner chooses between for the benchmark
-        for dt, width in (("f32", 0), ("f32", 128), ("bf16", 0), ("bf16", 256)):
+        forms = {"f32": (0, 256, 128), "bf16": (0, 512, 256)}
+        for dt, width in [(dt, w) for dt, ws in forms.items() for w in ws]:
             with cl.Context(0) as ctx:
                 ctx.set_slices(width)
                 ctx.build_graph(g).init(dim, dt, 11)
@@ -286,10 +288,10 @@ def test_chunglu10m_all_iterations_vs_oracle(cl, chunglu10m, capsys):
         in_sample = np.isin(rows, sample)
         in_top = np.isin(rows, top)
         for name, m in (("random 100k", in_sample), ("top-1000 degree", in_top)):
-            for (w32, w16) in ((0, 0), (128, 256)):
+            for (w32, w16) in zip(forms["f32"], forms["bf16"]):
                 e32 = float(np.abs(got["f32", w32][m] - want[m]).max())
                 e16, c16 = rowwise_report(got["bf16", w16][m], want[m])
-                form = "whole rows" if not w32 else "slices"
+                form = "whole rows" if not w32 else f"slices of {4 * w32} bytes"
                 print(f"chunglu10m k={k} vs FP64 oracle, {name} rows, {form}: FP32 max-abs "
                       f"{e32:.3e}; BF16 max-abs {e16:.3e} min-cos {c16:.7f}", flush=True)
                 assert e32 <= F32_TOL
