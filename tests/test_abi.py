@@ -134,3 +134,16 @@ def test_noalloc_limits_without_gpu(lib):
     assert f(0, 10, 10, 5, ids, ids, None, None, 16, 16, 0, out, 16, None) == _lib.E_INVAL
     assert f(0, 10, 10, 5, ids, ids, None, T, 20, 16, 0, out, 16, None) == _lib.E_INVAL  # ld_in
     assert f(0, 10, 10, 5, None, ids, None, T, 16, 16, 0, out, 16, None) == _lib.E_INVAL
+
+
+def test_binding_constants_match_the_header():
+    """Flags, storage types and the automatic slice width of the binding are
+    the header's."""
+    from paper_2102_02302_amd import _lib
+    text = open(HEADER).read()
+    want = {"CLEORA_SLICES_AUTO": _lib.SLICES_AUTO, "CLEORA_DIRECTED": _lib.DIRECTED,
+            "CLEORA_EMPTY_KEEP": _lib.EMPTY_KEEP, "CLEORA_F32": _lib.F32, "CLEORA_BF16": _lib.BF16}
+    for name, value in want.items():
+        m = re.search(rf"#define {name} \(?(-?\d+)", text) or re.search(
+            rf"\b{name}\s*=\s*(-?\d+)", text)
+        assert m and int(m.group(1)) == value, name
