@@ -256,9 +256,7 @@ void choose_slices(cleora_ctx *c, hipStream_t s)
         if (W > 0) widths.push_back(W);
     }
     if (!widths.empty() && c->n > 0) {
-        hipEvent_t a, b;
-        CLEORA_HIP(hipEventCreate(&a));
-        CLEORA_HIP(hipEventCreate(&b));
+        hipEvent_t a = nullptr, b = nullptr;
         auto timed = [&](int reps, const std::function<void()> &f) {
             f();  // warm-up
             CLEORA_HIP(hipEventRecord(a, s));
@@ -272,6 +270,8 @@ void choose_slices(cleora_ctx *c, hipStream_t s)
         const bool timing = c->timing;
         c->timing = false;
         try {
+            CLEORA_HIP(hipEventCreate(&a));
+            CLEORA_HIP(hipEventCreate(&b));
             const int cur = c->cur;
             const int32_t per_call = c->last_k > 0 ? c->last_k : 4;
             c->slice_cols = 0;
@@ -326,8 +326,8 @@ void choose_slices(cleora_ctx *c, hipStream_t s)
         } catch (...) {
             c->timing = timing;
             c->slice_cols = 0;
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
             throw;
         }
         c->timing = timing;

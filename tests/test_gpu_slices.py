@@ -9,7 +9,8 @@ bfloat16 within the stated bound of the oracle (max-abs 4e-3, minimum row
 cosine 0.9999) and 4e-3 of whole rows; a slice at least as wide as the row
 is whole rows (bit-identical); resumption, graph replay, eager launches,
 schedules and batch = solo bit-exact within the sliced mode; whole rows by
-default.
+default; the automatic mode keeps whole rows until the autotuner has
+chosen, then runs bit-identically to the chosen width set by hand.
 """
 
 import numpy as np
