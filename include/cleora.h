@@ -69,8 +69,10 @@ void cleora_destroy(cleora_ctx *ctx);
 /* Device bytes a context needs to embed a graph with n_nodes nodes and
  * n_edges input edges at the given dim and dtype (the memory model of
  * Section 4.5 -- one sparse matrix plus two N x d embedding buffers -- plus
- * the build and hub-row scratch of this implementation).  An upper bound,
- * used for admission decisions.  Returns 0 for invalid arguments. */
+ * the build and hub-row scratch of this implementation).  An upper bound
+ * for whole-row iterations, used for admission decisions; column slices
+ * (cleora_set_slices) add 4 bytes per stored entry and 8 per node.
+ * Returns 0 for invalid arguments. */
 size_t cleora_footprint_bytes(int64_t n_nodes, int64_t n_edges, uint32_t flags, int32_t dim,
                               int32_t dtype);
 

@@ -31,8 +31,10 @@ namespace {
 constexpr uint32_t ERR_ID = 1u, ERR_WEIGHT = 2u;
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 32;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // keys per block and pass
+constexpr int MG_ITEMS = 16;
+constexpr int MG_TILE = RS_THREADS * MG_ITEMS;  // entries per block of the merge
 constexpr int LONG_ROW = 4096;                  // rows summed in segments
 
 __device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     count[(int64_t)t * nblk + blockIdx.x] = (int32_t)s;
 }
 
-// Radix pass, step 3: stable scatter.  Wave w ranks the tile's keys
-// [w*512, (w+1)*512) in rounds of 64 (by round, then lane), keeping running
+// Radix pass, step 3: stable scatter.  Wave w ranks the w-th quarter of
+// the tile's keys in rounds of 64 (by round, then lane), keeping running
 // per-digit counts in its own LDS row, so ranking needs no block barrier;
 // one per-digit prefix over the waves then gives every key its place in
 // the tile in input order.  Keys are staged in LDS in digit order and
@@ -251,12 +253,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 // Merging repeated pairs of the sorted keys (entries [0, total), invalid
 // keys last).  Entry i starts a merged entry (a run of equal keys) when it
 // is valid and differs from entry i - 1.  Block b covers indices
-// [b * RS_TILE, (b + 1) * RS_TILE) of [0, total], index total standing for
+// [b * MG_TILE, (b + 1) * MG_TILE) of [0, total], index total standing for
 // the end; wave w of the block a contiguous quarter of that, in rounds of 64.
 // A wave loads its keys once; entry i - 1 (and i + 1) come from the
 // neighbouring lane or round, and from memory only at the chunk's edges.
 struct MergeChunk {
-    uint64_t key[RS_ITEMS], prev[RS_ITEMS], hb[RS_ITEMS];
+    uint64_t key[MG_ITEMS], prev[MG_ITEMS], hb[MG_ITEMS];
 };
 
 __device__ __forceinline__ void load_chunk(const uint64_t *__restrict__ keys, int64_t wbase,
@@ -264,13 +266,13 @@ __device__ __forceinline__ void load_chunk(const uint64_t *__restrict__ keys, in
                                            MergeChunk &c)
 {
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
+    for (int i = 0; i < MG_ITEMS; ++i) {
         const int64_t idx = wbase + i * WAVE + lane;
         c.key[i] = idx < total ? keys[idx] : 0;
     }
     const uint64_t edge = wbase > 0 && wbase <= total ? keys[wbase - 1] : 0;
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
+    for (int i = 0; i < MG_ITEMS; ++i) {
         const int64_t idx = wbase + i * WAVE + lane;
         const uint64_t up = __shfl_up(c.key[i], 1, WAVE);
         const uint64_t carry = i == 0 ? edge : __shfl(c.key[i > 0 ? i - 1 : 0], WAVE - 1, WAVE);
@@ -285,15 +287,15 @@ __global__ __launch_bounds__(RS_THREADS) void k_merge_count(const uint64_t *__re
                                                             int64_t total, uint64_t invalid_key,
                                                             int64_t *__restrict__ hcount)
 {
-    constexpr int NW = RS_THREADS / WAVE, CHUNK = RS_TILE / NW;
+    constexpr int NW = RS_THREADS / WAVE, CHUNK = MG_TILE / NW;
     __shared__ uint32_t wsum[NW];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * CHUNK;
+    const int64_t wbase = (int64_t)blockIdx.x * MG_TILE + (int64_t)w * CHUNK;
     MergeChunk c;
     load_chunk(keys, wbase, total, invalid_key, lane, c);
     uint32_t cnt = 0;
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
+    for (int i = 0; i < MG_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
     if (t == 0) {
@@ -313,16 +315,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_merge(
     uint64_t invalid_key, int cb, int64_t n, const int64_t *__restrict__ hoff,
     int32_t *__restrict__ col_u, double *__restrict__ e_u, int64_t *__restrict__ rp)
 {
-    constexpr int NW = RS_THREADS / WAVE, CHUNK = RS_TILE / NW;
+    constexpr int NW = RS_THREADS / WAVE, CHUNK = MG_TILE / NW;
     __shared__ uint32_t wsum[NW];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int64_t wbase = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * CHUNK;
+    const int64_t wbase = (int64_t)blockIdx.x * MG_TILE + (int64_t)w * CHUNK;
     const uint64_t cmask = ((uint64_t)1 << cb) - 1;
     MergeChunk c;
     load_chunk(keys, wbase, total, invalid_key, lane, c);
     uint32_t cnt = 0;
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
+    for (int i = 0; i < MG_ITEMS; ++i) cnt += (uint32_t)__popcll(c.hb[i]);
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
     int64_t u0 = hoff[blockIdx.x];
@@ -332,14 +334,14 @@ __global__ __launch_bounds__(RS_THREADS) void k_merge(
     const int64_t after = wbase + CHUNK;
     const uint64_t edge_next = after < total ? keys[after] : 0;
 #pragma unroll
-    for (int i = 0; i < RS_ITEMS; ++i) {
+    for (int i = 0; i < MG_ITEMS; ++i) {
         const int64_t idx = wbase + i * WAVE + lane;
         const int64_t u = u0 + __popcll(c.hb[i] & lt);  // merged entries before idx
         u0 += __popcll(c.hb[i]);
         const uint64_t k = c.key[i];
         const uint64_t down = __shfl_down(k, 1, WAVE);
         const uint64_t carry =
-            i + 1 < RS_ITEMS ? __shfl(c.key[i + 1 < RS_ITEMS ? i + 1 : i], 0, WAVE) : edge_next;
+            i + 1 < MG_ITEMS ? __shfl(c.key[i + 1 < MG_ITEMS ? i + 1 : i], 0, WAVE) : edge_next;
         const uint64_t next = lane == WAVE - 1 ? carry : down;
         if ((c.hb[i] >> lane) & 1ull) {
             col_u[u] = (int32_t)(k & cmask);
@@ -628,7 +630,7 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
         }
     }
     // merge repeated pairs; row pointers
-    const int64_t nblk_m = ceil_div(total + 1, RS_TILE);  // indices [0, total]
+    const int64_t nblk_m = ceil_div(total + 1, MG_TILE);  // indices [0, total]
     int64_t *hcount = pos, *hoff = pos + nblk_m;           // nblk_m + (nblk_m + 1) entries
     k_merge_count<<<(unsigned)nblk_m, RS_THREADS, 0, s>>>(keys, total, invalid_key, hcount);
     CLEORA_LAUNCH_CHECK();
