@@ -47,40 +47,62 @@ __device__ __forceinline__ bool weight_ok(float x)
 // Keys of the stored entries: entry 2e is edge e as given, entry 2e+1 its
 // reverse (undirected graphs); directed graphs use entry e only.  Invalid
 // edges and a loop's second copy get invalid_key, which sorts last; the
-// number of valid entries is found after the sort.
-__global__ void k_make_keys(int64_t m, int64_t n_rows, int64_t n_cols,
-                            const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
-                            const float *__restrict__ w, int directed, int cb,
-                            uint64_t invalid_key, uint64_t *__restrict__ keys,
-                            float *__restrict__ wout, uint32_t *err)
+// number of valid entries is found after the sort.  Block b makes entries
+// [b * RS_TILE, (b + 1) * RS_TILE), one radix tile, and also counts their
+// first digits as the sort's first counting pass would:
+// count[d * nblk + b] = entries of tile b whose low 8 bits are d.
+__global__ __launch_bounds__(RS_THREADS) void k_make_keys(
+    int64_t m, int64_t n_rows, int64_t n_cols, const int32_t *__restrict__ src,
+    const int32_t *__restrict__ dst, const float *__restrict__ w, int directed, int cb,
+    uint64_t invalid_key, int64_t total, int64_t nblk, uint64_t *__restrict__ keys,
+    float *__restrict__ wout, int32_t *__restrict__ count, uint32_t *err)
 {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = src[e], b = dst[e];
-        bool ok = a >= 0 && a < n_rows && b >= 0 && b < n_cols;
-        if (!ok) atomicOr(err, ERR_ID);
-        float x = 1.0f;
-        if (w) {
-            x = w[e];
-            if (ok && !weight_ok(x)) {
-                atomicOr(err, ERR_WEIGHT);
-                ok = false;
+    __shared__ uint32_t h[RS_THREADS / WAVE][256];
+    const int t = threadIdx.x, w_ = t >> 6, lane = t & 63;
+    for (int i = t; i < (RS_THREADS / WAVE) * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t idx = base + i * RS_THREADS + t;  // entry
+        const bool valid = idx < total;
+        uint64_t key = 0;
+        if (valid) {
+            const int64_t e = directed ? idx : idx >> 1;
+            const bool rev = !directed && (idx & 1);
+            const int32_t a = src[e], b = dst[e];
+            bool ok = a >= 0 && a < n_rows && b >= 0 && b < n_cols;
+            if (!ok && !rev) atomicOr(err, ERR_ID);
+            float x = 1.0f;
+            if (w) {
+                x = w[e];
+                if (ok && !weight_ok(x)) {
+                    if (!rev) atomicOr(err, ERR_WEIGHT);
+                    ok = false;
+                }
             }
+            if (rev) key = ok && a != b ? ((uint64_t)b << cb) | (uint64_t)a : invalid_key;
+            else key = ok ? ((uint64_t)a << cb) | (uint64_t)b : invalid_key;
+            keys[idx] = key;
+            if (wout) wout[idx] = x;
         }
-        const uint64_t fwd = ok ? ((uint64_t)a << cb) | (uint64_t)b : invalid_key;
-        if (directed) {
-            keys[e] = fwd;
-            if (wout) wout[e] = x;
-        } else {
-            const bool rev_ok = ok && a != b;  // a loop is stored once
-            keys[2 * e] = fwd;
-            keys[2 * e + 1] = rev_ok ? ((uint64_t)b << cb) | (uint64_t)a : invalid_key;
-            if (wout) {
-                wout[2 * e] = x;
-                wout[2 * e + 1] = x;
-            }
+        // lanes with the same low digit add their number once
+        const uint32_t d = (uint32_t)key & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool on = (d >> bit) & 1u;
+            const uint64_t mk = __ballot(on);
+            peers &= on ? mk : ~mk;
         }
+        if (valid && (peers & ((1ull << lane) - 1ull)) == 0)
+            atomicAdd(&h[w_][d], (uint32_t)__popcll(peers));
     }
+    __syncthreads();
+    uint32_t c = 0;
+    for (int q = 0; q < RS_THREADS / WAVE; ++q) c += h[q][t];
+    count[(int64_t)t * nblk + blockIdx.x] = (int32_t)c;
+    (void)m;
 }
 
 // n_valid = number of sorted keys below invalid_key (one thread).
@@ -607,16 +629,18 @@ void build_graph(cleora_ctx *c, int64_t n, int64_t n_cols, int64_t m, const int3
     int64_t *pos = c->t_pos.as<int64_t>(), *ws = c->t_scan.as<int64_t>();
 
     CLEORA_HIP(hipMemsetAsync(small, 0, sizeof(int64_t) * 4, s));
-    if (m > 0) {
-        k_make_keys<<<grid_for(m, 256, 65536), 256, 0, s>>>(m, n, n_cols, src, dst, w, directed,
-                                                            cb, invalid_key, keys, wa, err);
-        CLEORA_LAUNCH_CHECK();
-    }
-    // stable LSD radix sort of the keys (and weights)
+    // stable LSD radix sort of the keys (and weights); the first pass's
+    // digit counts come with the keys
     if (total > 0) {
+        k_make_keys<<<(unsigned)nblk, RS_THREADS, 0, s>>>(m, n, n_cols, src, dst, w, directed, cb,
+                                                          invalid_key, total, nblk, keys, wa,
+                                                          count, err);
+        CLEORA_LAUNCH_CHECK();
         for (int shift = 0; shift < key_bits; shift += 8) {
-            k_rs_count<<<(unsigned)nblk, RS_THREADS, 0, s>>>(keys, total, shift, nblk, count);
-            CLEORA_LAUNCH_CHECK();
+            if (shift > 0) {
+                k_rs_count<<<(unsigned)nblk, RS_THREADS, 0, s>>>(keys, total, shift, nblk, count);
+                CLEORA_LAUNCH_CHECK();
+            }
             exclusive_scan(count, 256 * nblk, pos, ws, s);
             if (w)
                 k_rs_scatter<true><<<(unsigned)nblk, RS_THREADS, 0, s>>>(keys, wa, total, shift,
