@@ -58,7 +58,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_make_keys(
     float *__restrict__ wout, int32_t *__restrict__ count, uint32_t *err)
 {
     __shared__ uint32_t h[RS_THREADS / WAVE][256];
-    const int t = threadIdx.x, w_ = t >> 6, lane = t & 63;
+    const int t = threadIdx.x, w_ = t >> 6;
     for (int i = t; i < (RS_THREADS / WAVE) * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -86,17 +86,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_make_keys(
             keys[idx] = key;
             if (wout) wout[idx] = x;
         }
-        // lanes with the same low digit add their number once
-        const uint32_t d = (uint32_t)key & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool on = (d >> bit) & 1u;
-            const uint64_t mk = __ballot(on);
-            peers &= on ? mk : ~mk;
-        }
-        if (valid && (peers & ((1ull << lane) - 1ull)) == 0)
-            atomicAdd(&h[w_][d], (uint32_t)__popcll(peers));
+        if (valid) atomicAdd(&h[w_][(uint32_t)key & 255u], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
@@ -128,7 +118,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     for (int i = t; i < (RS_THREADS / WAVE) * 256; i += RS_THREADS) (&h[0][0])[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    const int lane = t & 63;
     // all of the tile's loads are issued before any digit is counted
     uint64_t key[RS_ITEMS];
 #pragma unroll
@@ -138,19 +127,11 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_count(const uint64_t *__restr
     }
 #pragma unroll
     for (int i = 0; i < RS_ITEMS; ++i) {
-        // lanes with the same digit (often all of them, in the high digits
-        // of row ids) are counted by one LDS add of their number
-        const bool valid = base + i * RS_THREADS + t < n;
-        const uint32_t d = (uint32_t)(key[i] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t mk = __ballot(bit);
-            peers &= bit ? mk : ~mk;
-        }
-        if (valid && (peers & ((1ull << lane) - 1ull)) == 0)
-            atomicAdd(&h[w][d], (uint32_t)__popcll(peers));
+        // one LDS add per key into the wave's own counts (finding a lane's
+        // digit peers by ballots first costs more VALU work than the
+        // conflicting adds it saves)
+        if (base + i * RS_THREADS + t < n)
+            atomicAdd(&h[w][(uint32_t)(key[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     uint32_t s = 0;
