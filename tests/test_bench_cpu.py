@@ -114,6 +114,22 @@ def test_traffic_only_while_the_kernel_source_matches(tmp_path, monkeypatch):
                                  "hbm_bytes_per_launch": 5.0}))
     assert bench._traffic("chunglu1m", "f32") == 5.0
     assert bench._traffic("chunglu10m", "f32") is None  # no summary for that workload
+    # sliced iterations use the summary of their own slicing (per slice launch)
+    sliced = tmp_path / "spmm_norm_chunglu1m_f32_slices128_pmc.json"
+    sliced.write_text(json.dumps({"kernel_source_sha256_16": bench.kernel_source_hash(),
+                                  "hbm_bytes_per_launch": 7.0}))
+    assert bench._traffic("chunglu1m", "f32", 128) == 7.0
+    assert bench._traffic("chunglu1m", "f32", 256) is None
+    assert bench._traffic("chunglu1m", "f32", 0) == 5.0
+
+
+def test_committed_sliced_counter_summaries():
+    # the slicings the autotuner may keep at the 10M-node workload have
+    # counter summaries of the current source
+    for dt, widths in (("f32", (128, 256)), ("bf16", (256, 512))):
+        for w in widths:
+            t = bench._traffic("chunglu10m", dt, w)
+            assert t is not None and t > 0, (dt, w)
 
 
 def test_every_trace_summary_is_of_the_current_source():
