@@ -402,12 +402,13 @@ __global__ void k_row_counts(int64_t n, const unsigned long long *__restrict__ n
     }
 }
 
-// deg(a) and M values, four rows per wave.  When all four rows hold at most
-// 16 (32) entries they are summed by 16- (32-) lane groups: a 64-lane
-// butterfly over a row that short only adds exact zeros in its first
-// steps, so the grouping gives the same bits.  Otherwise the rows take one
-// 64-lane pass each; rows longer than LONG_ROW are listed for the
-// segmented kernels.
+// deg(a) and M values, four rows per wave.  Rows of at most 16 (32)
+// entries are summed by 16- (32-) lane groups, whatever the other rows of
+// the wave hold: a 64-lane butterfly over a row that short only adds exact
+// zeros in its first steps, so the grouping gives the same bits.  Longer
+// rows take one 64-lane pass each, with the first 64 entries of all of
+// them loaded before any is reduced; rows longer than LONG_ROW are listed
+// for the segmented kernels.
 __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *__restrict__ rp,
                                                      const double *__restrict__ e_u,
                                                      float *__restrict__ val,
@@ -420,39 +421,66 @@ __global__ __launch_bounds__(256) void k_rowsum_wave(int64_t n, const int64_t *_
     if (r0 >= n) return;
     const int lane = threadIdx.x & 63;
     const int nr = (int)min((int64_t)4, n - r0);
-    int64_t maxlen = 0;
-    for (int q = 0; q < nr; ++q) maxlen = max(maxlen, rp[r0 + q + 1] - rp[r0 + q]);
-    if (maxlen <= 32) {
-        const int width = maxlen <= 16 ? 16 : 32, per = 64 / width;
-        const int q = lane / width, gl = lane % width;
-        for (int base = 0; base < nr; base += per) {
-            const int64_t row = r0 + base + q;
-            const bool in = base + q < nr;
-            const int64_t lo = in ? rp[row] : 0, hi = in ? rp[row + 1] : 0;
-            const bool has = lo + gl < hi;
-            const double e = has ? e_u[lo + gl] : 0.0;
-            const double s = width == 16 ? group_sum<16>(e) : group_sum<32>(e);
-            if (in && gl == 0) deg[row] = s;
-            if (has) val[lo + gl] = (float)(e / s);
-        }
-        return;
-    }
-    // the first 64 entries of all four rows are loaded before any is
-    // reduced (four independent loads in flight, not one after another)
     int64_t lo[4], hi[4];
-    double first[4];
+    bool mid = false, big = false;  // rows of 17..32, and of more than 32 entries
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         lo[q] = q < nr ? rp[r0 + q] : 0;
         hi[q] = q < nr ? rp[r0 + q + 1] : 0;
+        mid |= hi[q] - lo[q] > 16 && hi[q] - lo[q] <= 32;
+        big |= hi[q] - lo[q] > 32;
     }
+    {
+        // rows of at most 16 entries: 16 lanes each, all four at once
+        const int q = lane >> 4, gl = lane & 15;
+        const int64_t l = q == 0 ? lo[0] : q == 1 ? lo[1] : q == 2 ? lo[2] : lo[3];
+        const int64_t h = q == 0 ? hi[0] : q == 1 ? hi[1] : q == 2 ? hi[2] : hi[3];
+        const bool mine = q < nr && h - l <= 16;
+        const bool has = mine && l + gl < h;
+        const double e = has ? e_u[l + gl] : 0.0;
+        const double sum = group_sum<16>(e);
+        if (mine && gl == 0) deg[r0 + q] = sum;
+        if (has) val[l + gl] = (float)(e / sum);
+    }
+    if (mid) {
+        // rows of 17..32 entries: 32 lanes each, two at a time
+        const int half = lane >> 5, gl = lane & 31;
+        double e[2];
+        int64_t at[2];
+        bool mine[2], has[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        first[q] = lo[q] + lane < hi[q] && hi[q] - lo[q] <= LONG_ROW ? e_u[lo[q] + lane] : 0.0;
+        for (int p = 0; p < 2; ++p) {
+            const int q = 2 * p + half;
+            const int64_t l = half ? lo[2 * p + 1] : lo[2 * p];
+            const int64_t h = half ? hi[2 * p + 1] : hi[2 * p];
+            mine[p] = q < nr && h - l > 16 && h - l <= 32;
+            at[p] = l + gl;
+            has[p] = mine[p] && at[p] < h;
+            e[p] = has[p] ? e_u[at[p]] : 0.0;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const double sum = group_sum<32>(e[p]);
+            if (mine[p] && gl == 0) deg[r0 + 2 * p + half] = sum;
+            if (has[p]) val[at[p]] = (float)(e[p] / sum);
+        }
+    }
+    if (!big) return;
+    // longer rows: the first 64 entries of all of them are loaded before
+    // any is reduced (independent loads in flight, not one after another)
+    double first[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t len = hi[q] - lo[q];
+        first[q] = q < nr && len > 32 && len <= LONG_ROW && lo[q] + lane < hi[q]
+                       ? e_u[lo[q] + lane]
+                       : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (q >= nr) break;
         const int64_t row = r0 + q;
+        if (hi[q] - lo[q] <= 32) continue;
         if (hi[q] - lo[q] > LONG_ROW) {
             if (lane == 0) long_list[atomicAdd(long_count, 1)] = (int32_t)row;
             continue;
